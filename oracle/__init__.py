@@ -1,0 +1,55 @@
+"""CPU oracle for the spectral-element Poisson/Helmholtz solve (FP64, NumPy/SciPy).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+calls this package; only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark do.  It shares no code with the HIP path: it consumes the
+seeded inputs (coordinates, global ids, Dirichlet flags, fields) and computes
+everything else itself, in plain array code that follows the method's
+definitions in order:
+
+* ``gll``       Gauss-Lobatto-Legendre nodes, weights and the derivative matrix
+                (the nodal basis and quadrature of the method, Sec. 2.2);
+* ``geometry``  per-point metric of the element map by the chain rule
+                (Sec. 2.2), six symmetric factors G_ab and the mass B;
+* ``operator``  the matrix-free tensor-product element operator
+                A_e u = D^T (k G) D u + h2 B u (Sec. 2.2), its diagonal, and the
+                backward (derivative in k) contraction;
+* ``assembly``  direct-stiffness summation (gather-scatter, Sec. 2.2 paragraph
+                on the surface exchange), restriction to free nodes, and the
+                explicitly assembled sparse matrix for small meshes;
+* ``solvers``   Jacobi-preconditioned conjugate gradients (the pressure Poisson
+                solve, Sec. 2.2), fourth-kind Chebyshev acceleration
+                (Sec. 2.2), CG-Lanczos eigenvalue bound, null-space projection;
+* ``grad``      the adjoint gradient of a solve with respect to k and b.
+
+The paper names the method but prints none of its formulas; every function
+states the textbook definition it follows and each is pinned by a test under
+``tests/`` against closed forms, library routines or invariants.
+"""
+
+from .gll import gll_nodes_weights, deriv_matrix, deriv_matrix_barycentric, legendre
+from .geometry import geometric_factors
+from .operator import local_apply, local_diagonal, mass_apply, kgrad_contraction
+from .assembly import Numbering, explicit_matrix, element_matrices
+from .solvers import Problem, pcg, chebyshev_apply, lanczos_lmax
+from .grad import solve_and_adjoint_gradient
+
+__all__ = [
+    "gll_nodes_weights",
+    "deriv_matrix",
+    "deriv_matrix_barycentric",
+    "legendre",
+    "geometric_factors",
+    "local_apply",
+    "local_diagonal",
+    "mass_apply",
+    "kgrad_contraction",
+    "Numbering",
+    "explicit_matrix",
+    "element_matrices",
+    "Problem",
+    "pcg",
+    "chebyshev_apply",
+    "lanczos_lmax",
+    "solve_and_adjoint_gradient",
+]
