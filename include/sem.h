@@ -1,0 +1,227 @@
+/*
+ * sem.h -- C ABI of libsem: a matrix-free spectral-element Poisson/Helmholtz
+ * solve for AMD MI355X (gfx950).
+ *
+ * The discretisation is the one of the paper's solver (Sec. 2.2): N_e
+ * hexahedral elements of polynomial order N, Gauss-Lobatto-Legendre (GLL)
+ * nodes and quadrature, unknowns ordered as tensors (ijk, i fastest) on the
+ * reference cube [-1,1]^3, operators applied matrix-free as dense
+ * (N+1)x(N+1) contractions identical for all elements and carried to deformed
+ * elements by the chain rule.  The pressure Poisson solve is the stiffest part
+ * of each time step and is solved by preconditioned conjugate gradients
+ * (Sec. 2.2), with fourth-kind Chebyshev acceleration and FP32 preconditioner
+ * work "to save on memory bandwidth" (Sec. 2.2).
+ *
+ * Notation used below:
+ *   P   = (N+1)^3 local points per element, local index q = i + (N+1)(j + (N+1)k)
+ *   n_L = E * P local points; "local vector" = array [E][P] (C order)
+ *   copy-consistent local vector = all local copies of a global node hold the
+ *   same value.
+ *   G   = six geometric factors per local point, order (rr, rs, rt, ss, st, tt),
+ *         G_ab = rho_i rho_j rho_k detJ (grad a . grad b); B = rho_i rho_j rho_k detJ.
+ *   A_L = element (unassembled) operator:
+ *         A_L(k) u = sum_ab D_a^T diag(k G_ab) D_b u + h2 B u
+ *         (weak form of -div(k grad u) + h2 u);
+ *   Q^T = sum of local copies into global nodes, Q = copy back; R = drop the
+ *         Dirichlet nodes.  The assembled operator is A = R Q^T A_L Q R^T.
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented as DEVICE must point to device memory of the device
+ *     that was current at sem_setup_mesh; HOST pointers to host memory.
+ *   - The caller owns every vector it passes.  The library owns the mesh
+ *     handle and everything inside it (geometry, numbering, work space) and
+ *     releases it in sem_free_mesh.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work on it and return without waiting unless documented as blocking.
+ *     A mesh handle is used from one stream at a time (its work space is
+ *     per handle).
+ *   - Errors: every call returns a sem_status; on SEM_EINVAL nothing was
+ *     written.  sem_last_error() returns a thread-local message describing
+ *     the last non-OK status of the calling thread.  HIP runtime failures
+ *     map to SEM_EDEVICE with the HIP error string in the message.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_EINVAL = -1,     /* invalid argument, mesh or option */
+  SEM_ENOMEM = -2,     /* device allocation failed */
+  SEM_EDEVICE = -3,    /* HIP runtime error */
+  SEM_ENOCONV = -4,    /* solve hit its iteration limit; x holds the last iterate */
+  SEM_EBREAKDOWN = -5, /* CG breakdown (p.Ap <= 0 or not finite); x holds the last iterate */
+  SEM_ENOTSUP = -6     /* valid request that this build does not implement */
+} sem_status;
+
+/* Arithmetic of an operator apply or of a preconditioner.
+ * SEM_FP64: data and arithmetic in double.
+ * SEM_FP32: data and arithmetic in float (vectors passed as float).
+ * SEM_BF16_MFMA / SEM_FP16_MFMA: float data; the (N+1)x(N+1) derivative
+ *   contractions run on the matrix cores with bf16/fp16 operands and fp32
+ *   accumulation.  Only meaningful inside the preconditioner. */
+typedef enum { SEM_FP64 = 0, SEM_FP32 = 1, SEM_BF16_MFMA = 2, SEM_FP16_MFMA = 3 } sem_prec;
+
+typedef struct sem_mesh sem_mesh; /* opaque, library-owned */
+
+/* Mesh description (Sec. 2.2: N_e hexahedra of order N, ijk ordering). */
+typedef struct {
+  int32_t N;                /* polynomial order, 1 <= N <= 10 (the solver family uses p <= 10, Sec. 4.1) */
+  int64_t E;                /* number of elements, >= 1, E*(N+1)^3 < 2^31 */
+  const double* xyz;        /* HOST [E][P][3]: physical coordinates of every local node */
+  const int64_t* gid;       /* HOST [E][P]: global node id >= 0; equal ids = one unknown
+                               (periodicity is expressed by equal ids) */
+  const uint8_t* dirichlet; /* HOST [E][P] or NULL (no Dirichlet nodes): nonzero = homogeneous
+                               Dirichlet node; must agree between all copies of a node */
+} sem_mesh_desc;
+
+typedef struct {
+  int64_t E, n_local, n_unique, n_free, n_shared; /* n_shared: unique nodes with >1 copy */
+  int32_t N;
+  int32_t has_nullspace; /* 1 if no Dirichlet node: the constant is in the kernel for h2 = 0 */
+} sem_mesh_info;
+
+typedef enum { SEM_PRECOND_JACOBI = 0, SEM_PRECOND_CHEBYSHEV = 1 } sem_precond;
+typedef enum { SEM_SOLVE_CG = 0, SEM_SOLVE_MIXED_IR = 1 } sem_solve_mode;
+
+typedef struct {
+  int32_t mode;         /* sem_solve_mode.  CG: FP64 (flexible when preconditioned by Chebyshev)
+                           conjugate gradients on the assembled system.  MIXED_IR: FP64 iterative
+                           refinement (true residual, update and norms in FP64) around an inner
+                           FP32 preconditioned CG. */
+  int32_t precond;      /* sem_precond of the CG (mode CG) or of the inner CG (MIXED_IR) */
+  int32_t precond_prec; /* sem_prec of the Chebyshev preconditioner.  Mode CG: SEM_FP64 or SEM_FP32
+                           (FP64 CG with an FP32 preconditioner); MIXED_IR: SEM_FP32 */
+  int32_t cheb_order;   /* Chebyshev order m >= 1 (m-1 operator applies per call); default 3 */
+  double lmax;          /* Chebyshev bound rho_hat >= lambda_max(D^-1 A); <= 0: 1.1 x a
+                           20-step CG-Lanczos estimate (cached per mesh for k == NULL) */
+  double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2 over the free unique nodes */
+  int32_t max_iter;     /* CG iteration limit (mode CG) or total inner-iteration limit (MIXED_IR) */
+  int32_t fixed_iters;  /* mode CG only: 1 = run exactly max_iter iterations (no early exit) */
+  double inner_rtol;    /* MIXED_IR: relative residual reduction of each inner solve (default 1e-5) */
+  int32_t max_outer;    /* MIXED_IR: refinement step limit (default 30) */
+  int32_t check_every;  /* iterations between convergence read-backs (0 = automatic) */
+  int32_t profile;      /* 1: time every FP64 operator-apply kernel with HIP events into stats */
+  double* residual_history; /* HOST, nullable, length max_iter + 1: ||r_i||_2 of the CG
+                               recurrence (mode CG) */
+} sem_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* CG iterations (mode CG) or total inner iterations (MIXED_IR) */
+  int32_t outer_iters;  /* MIXED_IR refinement steps (0 in mode CG) */
+  int32_t operator_applies;  /* FP64 + low-precision operator applies */
+  int32_t converged;    /* 1 if the tolerance was met */
+  double rel_res;       /* final ||r|| / ||b|| of the recurrence (mode CG) or of the FP64 true
+                           residual (MIXED_IR) */
+  double time_ms;       /* wall time of the solve on the stream (HIP events) */
+  double lmax;          /* Chebyshev bound used (0 for Jacobi) */
+  double ax_ms;         /* profile = 1: summed duration of FP64 operator kernels */
+  int32_t ax_launches;  /* profile = 1: number of FP64 operator kernels timed */
+  int32_t pad_;
+} sem_solve_stats;
+
+/* Fill `opts` with defaults: mode CG, Jacobi, FP64, order 3, rtol 1e-10,
+ * max_iter 10000, inner_rtol 1e-5, max_outer 30. */
+void sem_solve_opts_default(sem_solve_opts* opts);
+
+/* HOST-only.  GLL nodes xi[N+1] (ascending), weights rho[N+1] and derivative
+ * matrix D[(N+1)*(N+1)] with D[i*(N+1)+j] = l_j'(xi_i) for 1 <= N <= 10 (the
+ * nodal basis and quadrature of Sec. 2.2).  Any output may be NULL. */
+sem_status sem_gll(int32_t N, double* xi, double* rho, double* D);
+
+/* HOST-only.  The numbering sem_setup_mesh builds from gid/dirichlet:
+ * free_index[E*P] (HOST, caller-allocated) receives for each local point the
+ * index of its free unique node in first-touch order, or -1 for Dirichlet
+ * nodes; n_unique / n_free / n_shared receive the counts.  Validates as
+ * sem_setup_mesh does (gid >= 0, consistent Dirichlet flags). */
+sem_status sem_host_numbering(int32_t N, int64_t E, const int64_t* gid, const uint8_t* dirichlet,
+                              int32_t* free_index, int64_t* n_unique, int64_t* n_free,
+                              int64_t* n_shared);
+
+/* Build a mesh handle on the current HIP device: uploads the nodes,
+ * computes G and B on the device (chain rule, Sec. 2.2), builds the
+ * gather-scatter tables and checks detJ > 0 at every point (SEM_EINVAL
+ * otherwise).  Blocks until done.  *out receives the handle. */
+sem_status sem_setup_mesh(const sem_mesh_desc* desc, void* stream, sem_mesh** out);
+
+/* Release a handle (NULL is allowed).  Waits for the device. */
+sem_status sem_free_mesh(sem_mesh* mesh);
+
+sem_status sem_get_info(const sem_mesh* mesh, sem_mesh_info* info);
+
+/* Copy the geometric factors to caller buffers: G DEVICE double [E][6][P],
+ * B DEVICE double [E][P] (either may be NULL).  Stream-ordered. */
+sem_status sem_get_geometry(const sem_mesh* mesh, double* G, double* B, void* stream);
+
+/* w = A_L(k) u, the element operator of Sec. 2.2 applied to every element
+ * (unassembled).  u, w: DEVICE [E][P] of double (SEM_FP64) or float
+ * (SEM_FP32); k: DEVICE [E][P] of the same type or NULL (k = 1); h2 >= 0.
+ * w must not alias u. */
+sem_status sem_ax(const sem_mesh* mesh, const void* u, void* w, const void* k, double h2,
+                  sem_prec prec, void* stream);
+
+/* w = B u (the diagonal GLL mass matrix), DEVICE [E][P], FP64 or FP32. */
+sem_status sem_mass(const sem_mesh* mesh, const void* u, void* w, sem_prec prec, void* stream);
+
+/* Direct-stiffness summation v <- Q Q^T v in place: every local copy of a
+ * global node receives the sum over its copies, summed in ascending local
+ * index order (deterministic).  v: DEVICE [E][P], FP64 or FP32. */
+sem_status sem_gs(const sem_mesh* mesh, void* v, sem_prec prec, void* stream);
+
+/* Zero every local copy of a Dirichlet node, in place (R^T R on copies). */
+sem_status sem_mask(const sem_mesh* mesh, void* v, sem_prec prec, void* stream);
+
+/* dinv = inverse of the assembled diagonal of A(k) = R Q^T A_L(k) Q R^T at
+ * every local copy (0 at Dirichlet nodes): the Jacobi preconditioner.
+ * k: DEVICE double [E][P] or NULL; dinv: DEVICE double [E][P]. */
+sem_status sem_jacobi_inverse(const sem_mesh* mesh, const double* k, double h2, double* dinv,
+                              void* stream);
+
+/* z = p_m(S A) S r: the fourth-kind Chebyshev preconditioner of order m for
+ * the assembled operator, S = Jacobi (Sec. 2.2 names this acceleration;
+ * recurrence of Lottes 2022).  r, z: DEVICE double [E][P] copy-consistent
+ * (values at Dirichlet copies ignored / returned 0).  lmax > 0 is the bound
+ * rho_hat.  prec: SEM_FP64 or SEM_FP32 (internal vectors and operator).
+ * Stream-ordered. */
+sem_status sem_cheb_apply(const sem_mesh* mesh, const double* r, double* z, const double* k,
+                          double h2, int32_t order, double lmax, sem_prec prec, void* stream);
+
+/* *lmax = largest eigenvalue estimate of D^-1 A from `steps` Jacobi-CG
+ * iterations (CG-Lanczos tridiagonal), started from a fixed pseudo-random
+ * vector.  Blocks. */
+sem_status sem_lmax_estimate(const sem_mesh* mesh, const double* k, double h2, int32_t steps,
+                             double* lmax, void* stream);
+
+/* Solve A(k) x = b with A = R Q^T A_L(k) Q R^T (the pressure-Poisson /
+ * Helmholtz solve of Sec. 2.2).  b, x: DEVICE double [E][P] copy-consistent
+ * (b is read as the mean of its copies; Dirichlet entries ignored); x holds
+ * x0 on entry (NULL-free: pass zeros for x0 = 0) and the copy-consistent
+ * solution on return (0 at Dirichlet nodes).  With no Dirichlet node and
+ * h2 = 0 the constant mode is removed from b and from x (zero mean over the
+ * unique nodes).  k: DEVICE double [E][P] or NULL.  Blocks the host (it reads
+ * residual norms).  stats may be NULL.  Returns SEM_ENOCONV / SEM_EBREAKDOWN
+ * with x = last iterate and stats filled. */
+sem_status sem_pcg_solve(const sem_mesh* mesh, const double* b, double* x, const double* k,
+                         double h2, const sem_solve_opts* opts, sem_solve_stats* stats,
+                         void* stream);
+
+/* Backward of w = A_L(k) u for a cotangent wbar (all DEVICE double [E][P]):
+ *   ubar = A_L(k) wbar                (A_L is symmetric)           if ubar != NULL
+ *   kbar_q = sum_ab (D_a wbar)_q G_ab,q (D_b u)_q                   if kbar != NULL
+ * so that <wbar, A_L(dk) u> = <kbar, dk>.  Stream-ordered. */
+sem_status sem_ax_backward(const sem_mesh* mesh, const double* u, const double* wbar,
+                           const double* k, double h2, double* ubar, double* kbar, void* stream);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H */

@@ -1,0 +1,702 @@
+// The C entry points of libsem (declared and documented in include/sem.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "solver.hpp"
+
+namespace sem {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+sem_status fail(sem_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+sem_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? SEM_ENOMEM : SEM_EDEVICE;
+}
+
+sem_status DevBuf::ensure(size_t nbytes) {
+  if (nbytes <= bytes && p) return SEM_OK;
+  release();
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return hip_fail(e, "hipMalloc");
+  }
+  bytes = nbytes;
+  return SEM_OK;
+}
+
+template <typename T>
+static sem_status upload(DevBuf& d, const std::vector<T>& h, hipStream_t s) {
+  sem_status st = d.ensure(std::max<size_t>(h.size(), 1) * sizeof(T));
+  if (st) return st;
+  if (!h.empty()) SEM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return SEM_OK;
+}
+
+// --------------------------------------------------------- shared pieces
+
+static SolveWork& work_of(const sem_mesh* m) {
+  sem_mesh* mm = const_cast<sem_mesh*>(m);
+  if (!mm->work) mm->work = new SolveWork();
+  return *mm->work;
+}
+
+// inverse of the assembled diagonal on the free nodes (FP64 + FP32 copy)
+static sem_status prepare_dinv(const sem_mesh* m, SolveWork& W, const double* k, double h2,
+                               hipStream_t s) {
+  double* dinv = W.vec<double>(W.dinv, m->n_free);
+  float* dinv32 = W.vec<float>(W.dinv32, m->n_free);
+  double* dL = W.vec<double>(W.wL, m->nL);
+  if (!dinv || !dinv32 || !dL) return fail(SEM_ENOMEM, "work space");
+  sem_mesh* mm = const_cast<sem_mesh*>(m);
+  if (!k && mm->dinv_valid && mm->cached_h2 == h2) return SEM_OK;
+  SEM_HIP(launch_local_diag(m, k, h2, dL, s));
+  SEM_HIP((launch_free_sum<double, double>(m, dL, dinv, s)));
+  SEM_HIP(launch_reciprocal_mask(dinv, dinv32, m->n_free, s));
+  mm->dinv_valid = (k == nullptr);
+  mm->cached_h2 = h2;
+  return SEM_OK;
+}
+
+static Op<double> op64_of(const sem_mesh* m, const double* k, double h2) {
+  Op<double> o;
+  o.G = m->G64.as<double>();
+  o.B = m->B64.as<double>();
+  o.D = m->D64.as<double>();
+  o.k = k;
+  o.h2 = h2;
+  return o;
+}
+
+static sem_status op32_of(const sem_mesh* m, SolveWork& W, const double* k, double h2,
+                          hipStream_t s, Op<float>& o) {
+  o.G = m->G32.as<float>();
+  o.B = m->B32.as<float>();
+  o.D = m->D32.as<float>();
+  o.h2 = (float)h2;
+  o.k = nullptr;
+  if (k) {
+    float* k32 = W.vec<float>(W.k32, m->nL);
+    if (!k32) return fail(SEM_ENOMEM, "work space");
+    SEM_HIP((launch_convert<double, float>(k, k32, m->nL, 1.0, s)));
+    o.k = k32;
+  }
+  return SEM_OK;
+}
+
+// largest eigenvalue of a symmetric tridiagonal matrix by Sturm-sequence bisection
+static double tridiag_lmax(const std::vector<double>& a, const std::vector<double>& b) {
+  const int n = (int)a.size();
+  if (n == 0) return 0.0;
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+      q = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0.0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(hi), 1.0); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) == n) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+static sem_status estimate_lmax(const sem_mesh* m, SolveWork& W, const double* k, double h2,
+                                int steps, double* out, hipStream_t s) {
+  sem_mesh* mm = const_cast<sem_mesh*>(m);
+  if (!k && mm->cached_lmax > 0.0 && mm->cached_lmax_h2 == h2 && steps == 20) {
+    *out = mm->cached_lmax;
+    return SEM_OK;
+  }
+  sem_status st = W.init(m, std::max(steps, 1));
+  if (st) return st;
+  if ((st = prepare_dinv(m, W, k, h2, s))) return st;
+  const bool neumann = m->nullspace && h2 == 0.0;
+  double* b = W.vec<double>(W.tmpf, m->n_free);
+  CgArgs<double, double> a;
+  a.op = op64_of(m, k, h2);
+  a.b = b;
+  a.x = W.vec<double>(W.x, m->n_free);
+  a.r = W.vec<double>(W.r, m->n_free);
+  a.p = W.vec<double>(W.p, m->n_free);
+  a.w = W.vec<double>(W.w, m->n_free);
+  a.z = W.vec<double>(W.z, m->n_free);
+  a.wL = W.vec<double>(W.wL, m->nL);
+  a.dinv = W.dinv.as<double>();
+  if (!b || !a.x || !a.r || !a.p || !a.w || !a.z || !a.wL) return fail(SEM_ENOMEM, "work space");
+  SEM_HIP(launch_pseudo_random(b, m->n_free, 0x5eed5eedull, s));
+  if (neumann && (st = free_remove_mean_f64(m, W, b, s))) return st;
+  a.precond = SEM_PRECOND_JACOBI;
+  a.rtol = 0.0;
+  a.max_it = steps;
+  a.fixed = true;
+  a.x_zero = true;
+  a.neumann = neumann;
+  std::vector<double> al, be;
+  a.alpha_out = &al;
+  a.beta_out = &be;
+  CgResult res;
+  if ((st = cg_solve<double, double>(m, W, a, res, s))) return st;
+  // CG-Lanczos tridiagonal: T_jj = 1/a_j + b_{j-1}/a_{j-1}, T_{j,j+1} = sqrt(b_j)/a_j
+  int n = (int)al.size();
+  for (int j = 0; j < n; ++j)
+    if (!(al[j] > 0.0) || !std::isfinite(al[j])) {
+      n = j;
+      break;
+    }
+  if (n == 0) return fail(SEM_EBREAKDOWN, "eigenvalue estimate: CG produced no coefficient");
+  std::vector<double> diag(n), off(std::max(n - 1, 0));
+  for (int j = 0; j < n; ++j) {
+    diag[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < n) off[j] = std::sqrt(std::max(be[j], 0.0)) / al[j];
+  }
+  *out = tridiag_lmax(diag, off);
+  if (!k && steps == 20) {
+    mm->cached_lmax = *out;
+    mm->cached_lmax_h2 = h2;
+  }
+  return SEM_OK;
+}
+
+static bool prec_ok(sem_prec p) { return p == SEM_FP64 || p == SEM_FP32; }
+
+static sem_status check_mesh(const sem_mesh* m) {
+  if (!m) return fail(SEM_EINVAL, "mesh is NULL");
+  return SEM_OK;
+}
+
+}  // namespace sem
+
+sem_mesh::~sem_mesh() { delete work; }
+
+using namespace sem;
+
+extern "C" {
+
+void sem_solve_opts_default(sem_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->mode = SEM_SOLVE_CG;
+  o->precond = SEM_PRECOND_JACOBI;
+  o->precond_prec = SEM_FP64;
+  o->cheb_order = 3;
+  o->lmax = 0.0;
+  o->rtol = 1e-10;
+  o->max_iter = 10000;
+  o->fixed_iters = 0;
+  o->inner_rtol = 1e-5;
+  o->max_outer = 30;
+  o->check_every = 0;
+  o->profile = 0;
+  o->residual_history = nullptr;
+}
+
+const char* sem_last_error(void) { return g_last_error.c_str(); }
+
+sem_status sem_gll(int32_t N, double* xi, double* rho, double* D) {
+  g_last_error.clear();
+  return host_gll(N, xi, rho, D);
+}
+
+sem_status sem_host_numbering(int32_t N, int64_t E, const int64_t* gid, const uint8_t* dirichlet,
+                              int32_t* free_index, int64_t* n_unique, int64_t* n_free,
+                              int64_t* n_shared) {
+  HostNumbering hn;
+  sem_status st = build_numbering(N, E, gid, dirichlet, hn);
+  if (st) return st;
+  if (free_index) std::memcpy(free_index, hn.lmap.data(), hn.lmap.size() * sizeof(int32_t));
+  if (n_unique) *n_unique = hn.n_unique;
+  if (n_free) *n_free = hn.n_free;
+  if (n_shared) *n_shared = hn.n_shared;
+  return SEM_OK;
+}
+
+sem_status sem_setup_mesh(const sem_mesh_desc* desc, void* stream, sem_mesh** out) {
+  if (!desc || !out) return fail(SEM_EINVAL, "desc and out must not be NULL");
+  *out = nullptr;
+  const int N = desc->N;
+  const int64_t E = desc->E;
+  if (N < 1 || N > kMaxOrder) return fail(SEM_EINVAL, "N must be in [1, 10]");
+  if (E < 1) return fail(SEM_EINVAL, "E must be >= 1");
+  if (!desc->xyz || !desc->gid) return fail(SEM_EINVAL, "xyz and gid must not be NULL");
+  const int64_t P = (int64_t)(N + 1) * (N + 1) * (N + 1);
+  if (E > (int64_t)0x7fffffff / P) return fail(SEM_EINVAL, "E*(N+1)^3 must be < 2^31");
+  const int64_t nL = E * P;
+  for (int64_t a = 0; a < 3 * nL; ++a)
+    if (!std::isfinite(desc->xyz[a])) return fail(SEM_EINVAL, "xyz holds a non-finite value");
+
+  HostNumbering hn;
+  sem_status st = build_numbering(N, E, desc->gid, desc->dirichlet, hn);
+  if (st) return st;
+
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<sem_mesh> m(new sem_mesh());
+  m->N = N;
+  m->n1 = N + 1;
+  m->P = (int)P;
+  m->E = E;
+  m->nL = nL;
+  m->n_unique = hn.n_unique;
+  m->n_free = hn.n_free;
+  m->n_shared = hn.n_shared;
+  m->n_dloc = (int64_t)hn.dlist.size();
+  m->nullspace = (hn.n_free == hn.n_unique);
+  SEM_HIP(hipGetDevice(&m->device));
+
+  const int n1 = N + 1;
+  std::vector<double> Dh(n1 * n1 + n1);
+  if ((st = host_gll(N, nullptr, Dh.data() + n1 * n1, Dh.data()))) return st;
+  std::memcpy(m->h_D, Dh.data(), n1 * n1 * sizeof(double));
+  std::vector<float> D32(n1 * n1);
+  for (int a = 0; a < n1 * n1; ++a) D32[a] = (float)Dh[a];
+  if ((st = upload(m->D64, Dh, s)) || (st = upload(m->D32, D32, s))) return st;
+
+  if ((st = m->G64.ensure((size_t)E * 6 * P * sizeof(double))) ||
+      (st = m->B64.ensure((size_t)nL * sizeof(double))) ||
+      (st = m->G32.ensure((size_t)E * 6 * P * sizeof(float))) ||
+      (st = m->B32.ensure((size_t)nL * sizeof(float))))
+    return st;
+  {
+    DevBuf dxyz, dbad;
+    if ((st = dxyz.ensure((size_t)3 * nL * sizeof(double))) || (st = dbad.ensure(sizeof(int))))
+      return st;
+    SEM_HIP(hipMemcpyAsync(dxyz.p, desc->xyz, (size_t)3 * nL * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+    SEM_HIP(launch_fill<int>(dbad.as<int>(), 1, 0, s));
+    SEM_HIP(launch_geometry(m.get(), dxyz.as<double>(), m->G64.as<double>(), m->B64.as<double>(),
+                            m->G32.as<float>(), m->B32.as<float>(), dbad.as<int>(), s));
+    int bad = 0;
+    SEM_HIP(hipMemcpyAsync(&bad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    if (bad > 0)
+      return fail(SEM_EINVAL, "element map is not orientation-preserving (detJ <= 0) at " +
+                                  std::to_string(bad) + " points");
+  }
+  if ((st = upload(m->lmap, hn.lmap, s)) || (st = upload(m->fseg, hn.fseg, s)) ||
+      (st = upload(m->fperm, hn.fperm, s)) || (st = upload(m->gseg, hn.gseg, s)) ||
+      (st = upload(m->gperm, hn.gperm, s)) || (st = upload(m->dlist, hn.dlist, s)))
+    return st;
+  SEM_HIP(hipStreamSynchronize(s));
+  *out = m.release();
+  return SEM_OK;
+}
+
+sem_status sem_free_mesh(sem_mesh* mesh) {
+  if (!mesh) return SEM_OK;
+  (void)hipDeviceSynchronize();
+  delete mesh;
+  return SEM_OK;
+}
+
+sem_status sem_get_info(const sem_mesh* m, sem_mesh_info* info) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!info) return fail(SEM_EINVAL, "info is NULL");
+  info->E = m->E;
+  info->n_local = m->nL;
+  info->n_unique = m->n_unique;
+  info->n_free = m->n_free;
+  info->n_shared = m->n_shared;
+  info->N = m->N;
+  info->has_nullspace = m->nullspace ? 1 : 0;
+  return SEM_OK;
+}
+
+sem_status sem_get_geometry(const sem_mesh* m, double* G, double* B, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (G)
+    SEM_HIP(hipMemcpyAsync(G, m->G64.p, (size_t)m->E * 6 * m->P * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  if (B)
+    SEM_HIP(hipMemcpyAsync(B, m->B64.p, (size_t)m->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return SEM_OK;
+}
+
+sem_status sem_ax(const sem_mesh* m, const void* u, void* w, const void* k, double h2,
+                  sem_prec prec, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!u || !w) return fail(SEM_EINVAL, "u and w must not be NULL");
+  if (u == w) return fail(SEM_EINVAL, "w must not alias u");
+  if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == SEM_FP64) {
+    e = launch_ax<double>(m, (const double*)u, nullptr, (double*)w, (const double*)k, h2,
+                          m->G64.as<double>(), m->B64.as<double>(), m->D64.as<double>(), s);
+  } else if (prec == SEM_FP32) {
+    e = launch_ax<float>(m, (const float*)u, nullptr, (float*)w, (const float*)k, (float)h2,
+                         m->G32.as<float>(), m->B32.as<float>(), m->D32.as<float>(), s);
+  } else if (prec == SEM_BF16_MFMA || prec == SEM_FP16_MFMA) {
+    return fail(SEM_ENOTSUP, "matrix-core precisions are not available for sem_ax in this build");
+  } else {
+    return fail(SEM_EINVAL, "unknown precision");
+  }
+  if (e != hipSuccess) return hip_fail(e, "sem_ax");
+  return SEM_OK;
+}
+
+sem_status sem_mass(const sem_mesh* m, const void* u, void* w, sem_prec prec, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!u || !w) return fail(SEM_EINVAL, "u and w must not be NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == SEM_FP64)
+    e = launch_mass<double>(m->nL, m->B64.as<double>(), (const double*)u, (double*)w, s);
+  else if (prec == SEM_FP32)
+    e = launch_mass<float>(m->nL, m->B32.as<float>(), (const float*)u, (float*)w, s);
+  else
+    return fail(SEM_EINVAL, "sem_mass supports SEM_FP64 and SEM_FP32");
+  if (e != hipSuccess) return hip_fail(e, "sem_mass");
+  return SEM_OK;
+}
+
+sem_status sem_gs(const sem_mesh* m, void* v, sem_prec prec, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!v) return fail(SEM_EINVAL, "v must not be NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == SEM_FP64) e = launch_gs_local<double>(m, (double*)v, s);
+  else if (prec == SEM_FP32) e = launch_gs_local<float>(m, (float*)v, s);
+  else return fail(SEM_EINVAL, "sem_gs supports SEM_FP64 and SEM_FP32");
+  if (e != hipSuccess) return hip_fail(e, "sem_gs");
+  return SEM_OK;
+}
+
+sem_status sem_mask(const sem_mesh* m, void* v, sem_prec prec, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!v) return fail(SEM_EINVAL, "v must not be NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == SEM_FP64) e = launch_mask_local<double>(m, (double*)v, s);
+  else if (prec == SEM_FP32) e = launch_mask_local<float>(m, (float*)v, s);
+  else return fail(SEM_EINVAL, "sem_mask supports SEM_FP64 and SEM_FP32");
+  if (e != hipSuccess) return hip_fail(e, "sem_mask");
+  return SEM_OK;
+}
+
+sem_status sem_jacobi_inverse(const sem_mesh* m, const double* k, double h2, double* dinv,
+                              void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!dinv) return fail(SEM_EINVAL, "dinv must not be NULL");
+  if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  SolveWork& W = work_of(m);
+  sem_status st = prepare_dinv(m, W, k, h2, s);
+  if (st) return st;
+  SEM_HIP((launch_free_to_local<double, double>(m, W.dinv.as<double>(), dinv, s)));
+  return SEM_OK;
+}
+
+sem_status sem_cheb_apply(const sem_mesh* m, const double* r, double* z, const double* k,
+                          double h2, int32_t order, double lmax, sem_prec prec, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!r || !z) return fail(SEM_EINVAL, "r and z must not be NULL");
+  if (order < 1) return fail(SEM_EINVAL, "order must be >= 1");
+  if (!(lmax > 0.0) || !std::isfinite(lmax)) return fail(SEM_EINVAL, "lmax must be > 0");
+  if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  if (!prec_ok(prec)) return fail(SEM_ENOTSUP, "sem_cheb_apply supports SEM_FP64 and SEM_FP32");
+  hipStream_t s = (hipStream_t)stream;
+  SolveWork& W = work_of(m);
+  sem_status st = W.init(m, 1);
+  if (st) return st;
+  if ((st = prepare_dinv(m, W, k, h2, s))) return st;
+  double* rf = W.vec<double>(W.tmpf, m->n_free);
+  double* zf = W.vec<double>(W.z, m->n_free);
+  if (!rf || !zf) return fail(SEM_ENOMEM, "work space");
+  SEM_HIP((launch_local_to_free_avg<double, double>(m, r, rf, s)));
+  if (prec == SEM_FP64) {
+    st = cheb_apply_dev<double, double>(m, W, op64_of(m, k, h2), W.dinv.as<double>(), rf, zf, order,
+                                        lmax, nullptr, nullptr, nullptr, s, nullptr);
+  } else {
+    Op<float> o32;
+    if ((st = op32_of(m, W, k, h2, s, o32))) return st;
+    st = cheb_apply_dev<double, float>(m, W, o32, W.dinv32.as<float>(), rf, zf, order, lmax,
+                                       nullptr, nullptr, nullptr, s, nullptr);
+  }
+  if (st) return st;
+  SEM_HIP((launch_free_to_local<double, double>(m, zf, z, s)));
+  return SEM_OK;
+}
+
+sem_status sem_lmax_estimate(const sem_mesh* m, const double* k, double h2, int32_t steps,
+                             double* lmax, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!lmax) return fail(SEM_EINVAL, "lmax must not be NULL");
+  if (steps < 1) return fail(SEM_EINVAL, "steps must be >= 1");
+  if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  return estimate_lmax(m, work_of(m), k, h2, steps, lmax, (hipStream_t)stream);
+}
+
+sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const double* k,
+                         double h2, const sem_solve_opts* opts_in, sem_solve_stats* stats,
+                         void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!b || !x) return fail(SEM_EINVAL, "b and x must not be NULL");
+  if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  sem_solve_opts opts;
+  if (opts_in) opts = *opts_in;
+  else sem_solve_opts_default(&opts);
+  if (opts.mode != SEM_SOLVE_CG && opts.mode != SEM_SOLVE_MIXED_IR)
+    return fail(SEM_EINVAL, "unknown solve mode");
+  if (opts.precond != SEM_PRECOND_JACOBI && opts.precond != SEM_PRECOND_CHEBYSHEV)
+    return fail(SEM_EINVAL, "unknown preconditioner");
+  if (opts.cheb_order < 1) return fail(SEM_EINVAL, "cheb_order must be >= 1");
+  if (opts.max_iter < 0) return fail(SEM_EINVAL, "max_iter must be >= 0");
+  if (!(opts.rtol >= 0.0)) return fail(SEM_EINVAL, "rtol must be >= 0");
+  if (opts.mode == SEM_SOLVE_MIXED_IR && opts.fixed_iters)
+    return fail(SEM_EINVAL, "fixed_iters is only available in mode CG");
+  if (opts.mode == SEM_SOLVE_MIXED_IR && !(opts.inner_rtol > 0.0 && opts.inner_rtol < 1.0))
+    return fail(SEM_EINVAL, "inner_rtol must be in (0, 1)");
+  if (opts.precond == SEM_PRECOND_CHEBYSHEV && !prec_ok((sem_prec)opts.precond_prec))
+    return fail(SEM_ENOTSUP, "Chebyshev precision must be SEM_FP64 or SEM_FP32");
+  if (opts.mode == SEM_SOLVE_MIXED_IR && opts.precond == SEM_PRECOND_CHEBYSHEV &&
+      opts.precond_prec != SEM_FP32)
+    return fail(SEM_EINVAL, "the inner solve of MIXED_IR runs in SEM_FP32");
+
+  hipStream_t s = (hipStream_t)stream;
+  SolveWork& W = work_of(m);
+  sem_status st = W.init(m, std::max(opts.max_iter, 1));
+  if (st) return st;
+  W.ev_used = 0;
+  hipEvent_t t0, t1;
+  SEM_HIP(hipEventCreate(&t0));
+  SEM_HIP(hipEventCreate(&t1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{t0, t1};
+
+  const bool neumann = m->nullspace && h2 == 0.0;
+  const bool cheb = opts.precond == SEM_PRECOND_CHEBYSHEV;
+  double lmax = opts.lmax;
+  if (cheb && !(lmax > 0.0)) {
+    double est = 0.0;
+    if ((st = estimate_lmax(m, W, k, h2, 20, &est, s))) return st;
+    lmax = 1.1 * est;
+  }
+  SEM_HIP(hipEventRecord(t0, s));
+  if ((st = prepare_dinv(m, W, k, h2, s))) return st;
+  const int64_t nf = m->n_free;
+  double* bf = W.vec<double>(W.bf, nf);
+  double* xf = W.vec<double>(W.x, nf);
+  if (!bf || !xf) return fail(SEM_ENOMEM, "work space");
+  SEM_HIP((launch_local_to_free_avg<double, double>(m, b, bf, s)));
+  SEM_HIP((launch_local_to_free_avg<double, double>(m, x, xf, s)));
+  if (neumann && (st = free_remove_mean_f64(m, W, bf, s))) return st;
+  double xd[3];
+  if ((st = free_dots_f64(m, W, xf, nullptr, xd, s))) return st;
+  const bool x_zero = (xd[0] == 0.0);
+  if (!std::isfinite(xd[0])) return fail(SEM_EINVAL, "x0 is not finite");
+
+  const Op<double> op64 = op64_of(m, k, h2);
+  Op<float> op32;
+  if ((st = op32_of(m, W, k, h2, s, op32))) return st;
+  const double* dinv = W.dinv.as<double>();
+  const float* dinv32 = W.dinv32.as<float>();
+
+  int iters = 0, outer = 0, applies = 0;
+  bool converged = false;
+  int fail_status = 0;
+  double rel = 0.0;
+
+  if (opts.mode == SEM_SOLVE_CG) {
+    CgArgs<double, double> a;
+    a.op = op64;
+    a.b = bf;
+    a.x = xf;
+    a.r = W.vec<double>(W.r, nf);
+    a.p = W.vec<double>(W.p, nf);
+    a.w = W.vec<double>(W.w, nf);
+    a.z = W.vec<double>(W.z, nf);
+    a.wL = W.vec<double>(W.wL, m->nL);
+    if (!a.r || !a.p || !a.w || !a.z || !a.wL) return fail(SEM_ENOMEM, "work space");
+    a.dinv = dinv;
+    a.precond = opts.precond;
+    a.cheb_order = opts.cheb_order;
+    if (cheb) {
+      const int order = opts.cheb_order;
+      if (opts.precond_prec == SEM_FP64) {
+        a.cheb = [op64, dinv, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
+                                           double* z, const CgScalars* sc, const double* wcg,
+                                           double* part, hipStream_t ss, int* ap) {
+          return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, sc, wcg,
+                                                part, ss, ap);
+        };
+      } else {
+        a.cheb = [op32, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
+                                             double* z, const CgScalars* sc, const double* wcg,
+                                             double* part, hipStream_t ss, int* ap) {
+          return cheb_apply_dev<double, float>(mm, WW, op32, dinv32, r, z, order, lmax, sc, wcg,
+                                               part, ss, ap);
+        };
+      }
+    }
+    a.rtol = opts.rtol;
+    a.max_it = opts.max_iter;
+    a.fixed = opts.fixed_iters != 0;
+    a.x_zero = x_zero;
+    a.neumann = neumann;
+    a.profile = opts.profile != 0;
+    a.check_every = opts.check_every;
+    a.hist = opts.residual_history;
+    CgResult res;
+    if ((st = cg_solve<double, double>(m, W, a, res, s))) return st;
+    iters = res.iters;
+    applies = res.applies;
+    converged = res.converged;
+    fail_status = res.status;
+    rel = res.bnorm > 0.0 ? res.rnorm / res.bnorm : 0.0;
+  } else {
+    // FP64 iterative refinement around an FP32 inner CG
+    double* r = W.vec<double>(W.r, nf);
+    float* b32 = W.vec<float>(W.r32, nf);
+    CgArgs<float, float> a;
+    a.op = op32;
+    a.b = b32;
+    a.x = W.vec<float>(W.x32, nf);
+    a.r = W.vec<float>(W.ri32, nf);
+    a.p = W.vec<float>(W.p32, nf);
+    a.w = W.vec<float>(W.w32, nf);
+    a.z = W.vec<float>(W.z32, nf);
+    a.wL = W.vec<float>(W.wL32, m->nL);
+    if (!r || !b32 || !a.x || !a.r || !a.p || !a.w || !a.z || !a.wL)
+      return fail(SEM_ENOMEM, "work space");
+    a.dinv = dinv32;
+    a.precond = opts.precond;
+    a.cheb_order = opts.cheb_order;
+    if (cheb) {
+      const int order = opts.cheb_order;
+      a.cheb = [op32, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const float* rr,
+                                           float* z, const CgScalars* sc, const float* wcg,
+                                           double* part, hipStream_t ss, int* ap) {
+        return cheb_apply_dev<float, float>(mm, WW, op32, dinv32, rr, z, order, lmax, sc, wcg, part,
+                                            ss, ap);
+      };
+    }
+    a.neumann = neumann;
+    a.x_zero = true;
+    a.fixed = false;
+    a.rtol = opts.inner_rtol;
+    a.check_every = opts.check_every;
+    double bd[3];
+    if ((st = free_dots_f64(m, W, bf, nullptr, bd, s))) return st;
+    const double bnorm = std::sqrt(bd[0]);
+    double rr_sum[2];
+    if (x_zero) {
+      SEM_HIP((launch_convert<double, double>(bf, r, nf, 1.0, s)));
+      rr_sum[0] = bd[0];
+      rr_sum[1] = bd[2];
+    } else {
+      if ((st = ir_residual(m, W, op64, xf, bf, r, rr_sum, s, opts.profile != 0))) return st;
+      ++applies;
+    }
+    if (bnorm == 0.0) {
+      SEM_HIP(launch_fill<double>(xf, nf, 0.0, s));
+      converged = true;
+    }
+    while (!converged) {
+      const double rnorm = std::sqrt(rr_sum[0]);
+      rel = rnorm / bnorm;
+      if (!std::isfinite(rel)) {
+        fail_status = 3;
+        break;
+      }
+      if (rel <= opts.rtol) {
+        converged = true;
+        break;
+      }
+      if (outer >= opts.max_outer || iters >= opts.max_iter) break;
+      const double shift = neumann ? rr_sum[1] / (double)nf : 0.0;
+      if ((st = ir_prepare(m, r, b32, shift, 1.0 / rnorm, s))) return st;
+      a.max_it = std::max(1, opts.max_iter - iters);
+      CgResult res;
+      if ((st = cg_solve<float, float>(m, W, a, res, s))) return st;
+      iters += res.iters;
+      applies += res.applies;
+      if (res.status == 2 || res.status == 3) {
+        fail_status = res.status;
+        break;
+      }
+      if ((st = ir_update(m, xf, a.x, rnorm, s))) return st;
+      if ((st = ir_residual(m, W, op64, xf, bf, r, rr_sum, s, opts.profile != 0))) return st;
+      ++applies;
+      ++outer;
+    }
+  }
+  if (neumann && (st = free_remove_mean_f64(m, W, xf, s))) return st;
+  SEM_HIP((launch_free_to_local<double, double>(m, xf, x, s)));
+  SEM_HIP(hipEventRecord(t1, s));
+  SEM_HIP(hipEventSynchronize(t1));
+  float ms = 0.f;
+  SEM_HIP(hipEventElapsedTime(&ms, t0, t1));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = iters;
+    stats->outer_iters = outer;
+    stats->operator_applies = applies;
+    stats->converged = converged ? 1 : 0;
+    stats->rel_res = rel;
+    stats->time_ms = ms;
+    stats->lmax = cheb ? lmax : 0.0;
+    double ax_ms = 0.0;
+    for (int i = 0; i + 1 < W.ev_used; i += 2) {
+      float d = 0.f;
+      if (hipEventElapsedTime(&d, W.ev[i], W.ev[i + 1]) == hipSuccess) ax_ms += d;
+    }
+    stats->ax_ms = ax_ms;
+    stats->ax_launches = W.ev_used / 2;
+  }
+  if (fail_status == 2 || fail_status == 3)
+    return fail(SEM_EBREAKDOWN, fail_status == 2 ? "CG breakdown: p.Ap <= 0"
+                                                 : "CG produced a non-finite value");
+  if (!converged && !opts.fixed_iters)
+    return fail(SEM_ENOCONV, "iteration limit reached before the tolerance");
+  return SEM_OK;
+}
+
+sem_status sem_ax_backward(const sem_mesh* m, const double* u, const double* wbar, const double* k,
+                           double h2, double* ubar, double* kbar, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!u || !wbar) return fail(SEM_EINVAL, "u and wbar must not be NULL");
+  if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  if (ubar == wbar) return fail(SEM_EINVAL, "ubar must not alias wbar");
+  hipStream_t s = (hipStream_t)stream;
+  if (ubar) {
+    hipError_t e = launch_ax<double>(m, wbar, nullptr, ubar, k, h2, m->G64.as<double>(),
+                                     m->B64.as<double>(), m->D64.as<double>(), s);
+    if (e != hipSuccess) return hip_fail(e, "sem_ax_backward (ubar)");
+  }
+  if (kbar) {
+    hipError_t e = launch_ax_kbar(m, u, wbar, kbar, s);
+    if (e != hipSuccess) return hip_fail(e, "sem_ax_backward (kbar)");
+  }
+  return SEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+// Internal declarations shared by the host drivers and the HIP kernels of libsem.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sem.h"
+
+namespace sem {
+
+constexpr int kMaxOrder = 10;           // the solver family uses p <= 10 (Sec. 4.1)
+constexpr int kVecBlock = 256;          // threads per block of the vector kernels
+constexpr int kReduceBlocks = 1024;     // fixed grid of reducing kernels (deterministic sums)
+constexpr int kMaxReduce = 4;           // values reduced per pass
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+sem_status fail(sem_status s, const std::string& msg);
+sem_status hip_fail(hipError_t e, const char* what);
+
+#define SEM_HIP(call)                                       \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return ::sem::hip_fail(e_, #call); \
+  } while (0)
+
+#define SEM_CHECK_LAUNCH(name)                                   \
+  do {                                                           \
+    hipError_t e_ = hipGetLastError();                           \
+    if (e_ != hipSuccess) return ::sem::hip_fail(e_, name);      \
+  } while (0)
+
+// ------------------------------------------------------ device allocation
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  sem_status ensure(size_t nbytes);  // grow-only
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ----------------------------------------------------------- host numbering
+struct HostNumbering {
+  int64_t n_unique = 0, n_free = 0, n_shared = 0;
+  std::vector<int32_t> lmap;          // [nL] free index (first-touch order) or -1
+  std::vector<int32_t> fseg, fperm;   // CSR over free unique nodes -> local copies (ascending)
+  std::vector<int32_t> gseg, gperm;   // CSR over shared unique nodes (all, incl. Dirichlet)
+  std::vector<int32_t> dlist;         // local indices of Dirichlet copies
+};
+sem_status build_numbering(int N, int64_t E, const int64_t* gid, const uint8_t* dirichlet,
+                           HostNumbering& out);
+sem_status host_gll(int N, double* xi, double* rho, double* D);
+
+// ------------------------------------------------------ device scalars
+// Scalars of a CG iteration, resident on the device: the vector kernels read
+// alpha/beta from here so the host never sits between two kernels of an
+// iteration; it only polls `done` every few iterations.
+struct CgScalars {
+  double rho;       // r.z of the current iterate
+  double alpha, beta;
+  double bb;        // ||b||^2
+  double tol2;      // (rtol ||b||)^2
+  double rr;        // ||r||^2 of the latest iterate
+  double mean_w;    // null-space projection: mean of w over unique nodes
+  double inv_n;     // 1 / n_free
+  double zw;        // flexible CG: z.w
+  double pad[3];
+  int32_t it;       // completed iterations
+  int32_t done;     // 1 = converged or failed: every later kernel of the solve is a no-op
+  int32_t status;   // 0 ok, 1 converged, 2 breakdown, 3 non-finite
+  int32_t max_it;
+  int32_t fixed;    // 1 = never stop before max_it
+  int32_t neumann;  // 1 = project out the constant mode
+  int32_t flexible; // 1 = Polak-Ribiere beta
+  int32_t pad2;
+};
+
+// ------------------------------------------------------------- the mesh
+struct SolveWork;
+
+}  // namespace sem
+
+struct sem_mesh {
+  int N = 0, n1 = 0, P = 0;
+  int64_t E = 0, nL = 0, n_unique = 0, n_free = 0, n_shared = 0, n_dloc = 0;
+  bool nullspace = false;
+  int device = 0;
+  double h_D[(sem::kMaxOrder + 1) * (sem::kMaxOrder + 1)];
+  sem::DevBuf D64, D32;                 // derivative matrix
+  sem::DevBuf G64, B64, G32, B32;       // geometry [E][6][P], [E][P]
+  sem::DevBuf lmap, fseg, fperm;        // solver numbering (free unique nodes)
+  sem::DevBuf gseg, gperm, dlist;       // local gather-scatter tables, Dirichlet copies
+  sem::DevBuf fcount;                   // copies per free node as double (for averaging)
+  // cached Jacobi inverse and Chebyshev bound for k == NULL
+  double cached_h2 = -1.0;
+  bool dinv_valid = false;
+  double cached_lmax_h2 = -1.0;
+  double cached_lmax = 0.0;
+  sem::SolveWork* work = nullptr;
+  ~sem_mesh();
+};
+
+namespace sem {
+
+// ----------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return hipGetLastError().
+
+// element operator, FP64/FP32; `lmap` != nullptr: gather the input from a
+// free-unique vector (x_L = x[lmap], 0 where lmap < 0)
+// `skip` (device, nullable): nonzero -> the kernel returns at once
+template <typename T>
+hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
+                     const T* G, const T* B, const T* D, hipStream_t s,
+                     const int32_t* skip = nullptr);
+hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_mass(int64_t n, const T* B, const T* u, T* w, hipStream_t s);
+
+// setup
+hipError_t launch_geometry(const sem_mesh* m, const double* xyz, double* G, double* B, float* G32,
+                           float* B32, int* bad_count, hipStream_t s);
+hipError_t launch_local_diag(const sem_mesh* m, const double* k, double h2, double* dL,
+                             hipStream_t s);
+
+// gather-scatter on local vectors
+template <typename T>
+hipError_t launch_gs_local(const sem_mesh* m, T* v, hipStream_t s);
+template <typename T>
+hipError_t launch_mask_local(const sem_mesh* m, T* v, hipStream_t s);
+
+// layout conversions between local copy-consistent vectors and free unique vectors
+template <typename Tin, typename Tout>
+hipError_t launch_local_to_free_avg(const sem_mesh* m, const Tin* vL, Tout* vf, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_free_to_local(const sem_mesh* m, const Tin* vf, Tout* vL, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_free_sum(const sem_mesh* m, const Tin* wL, Tout* wf, hipStream_t s);
+
+// generic small kernels
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_convert(const Tin* a, Tout* b, int64_t n, double scale, hipStream_t s);
+hipError_t launch_reciprocal_mask(double* d, float* d32, int64_t n, hipStream_t s);
+hipError_t launch_pseudo_random(double* v, int64_t n, uint64_t seed, hipStream_t s);
+
+}  // namespace sem

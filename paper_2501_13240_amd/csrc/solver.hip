@@ -1,0 +1,738 @@
+// Preconditioned conjugate gradients on the assembled operator (the pressure
+// Poisson solve of Sec. 2.2), fourth-kind Chebyshev acceleration of Jacobi
+// (Sec. 2.2), FP32 preconditioner work (Sec. 2.2), and FP64 iterative
+// refinement around an FP32 inner solve.
+//
+// Vectors of the solve live on the free unique nodes in first-touch order
+// (length n_free).  One iteration is
+//   ax (gathers p through lmap, writes the element-local result w_L)
+//   -> segmented sum w = R Q^T w_L fused with p.w
+//   -> alpha on the device -> x, r update fused with r.r (and r.S r)
+//   -> beta on the device -> p update.
+// All scalars stay on the device (CgScalars); the host only polls the `done`
+// flag every few iterations with one chunk of iterations always queued ahead,
+// and every kernel of a finished solve returns at once.  Reductions use a
+// fixed grid and a fixed summation order, so solves are bit-reproducible.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "solver.hpp"
+
+namespace sem {
+
+// ---------------------------------------------------------------- helpers
+namespace {
+
+#define GRID_STRIDE(idx, n)                                                        \
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (n); \
+       idx += (int64_t)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// per-block partial sums of NV values -> part[blockIdx.x * NV + a]
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* __restrict__ part) {
+  __shared__ double red[NV][kVecBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NV; ++a) {
+    const double x = wave_sum(v[a]);
+    if (lane == 0) red[a][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < kVecBlock / 64; ++w) s += red[threadIdx.x][w];
+    part[blockIdx.x * NV + threadIdx.x] = s;
+  }
+}
+
+// one block sums nblk partials in a fixed order; every thread gets S
+template <int NV>
+__device__ __forceinline__ void block_total(const double* __restrict__ part, int nblk,
+                                            double (&S)[NV]) {
+  __shared__ double red[NV][kVecBlock / 64];
+  __shared__ double tot[NV];
+  double v[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int a = 0; a < NV; ++a) v[a] += part[b * NV + a];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NV; ++a) {
+    const double x = wave_sum(v[a]);
+    if (lane == 0) red[a][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < kVecBlock / 64; ++w) s += red[threadIdx.x][w];
+    tot[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < NV; ++a) S[a] = tot[a];
+}
+
+__device__ __forceinline__ bool finite(double x) { return x == x && fabs(x) <= 1.7976931348623157e308; }
+
+// ------------------------------------------------------------- CG kernels
+
+// w = R Q^T w_L (segmented sum); partials of p.w, sum(w), sum(p)
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t* __restrict__ seg,
+                                                       const int32_t* __restrict__ perm,
+                                                       const T* __restrict__ wL,
+                                                       const T* __restrict__ p, T* __restrict__ w,
+                                                       double* __restrict__ part,
+                                                       const CgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  double v[3] = {0.0, 0.0, 0.0};
+  GRID_STRIDE(g, nf) {
+    const int32_t a = seg[g], b = seg[g + 1];
+    T s = T(0);
+    for (int32_t q = a; q < b; ++q) s += wL[perm[q]];
+    w[g] = s;
+    const double pg = (double)p[g];
+    v[0] += pg * (double)s;
+    v[1] += (double)s;
+    v[2] += pg;
+  }
+  block_partials<3>(v, part);
+}
+
+__global__ __launch_bounds__(kVecBlock) void k_alpha(const double* __restrict__ part, int nblk,
+                                                     CgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  double S[3];
+  block_total<3>(part, nblk, S);
+  if (threadIdx.x == 0) {
+    double pw = S[0], mw = 0.0;
+    if (sc->neumann) {
+      mw = S[1] * sc->inv_n;
+      pw -= mw * S[2];
+    }
+    sc->mean_w = mw;
+    if (!(pw > 0.0) || !finite(pw)) {
+      sc->status = 2;
+      sc->done = 1;
+      sc->alpha = 0.0;
+    } else {
+      sc->alpha = sc->rho / pw;
+    }
+  }
+}
+
+// x += alpha p;  r -= alpha (w - mean_w);  partials of r.r (and r.S r)
+template <typename T, bool JAC>
+__global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict__ x,
+                                                      const T* __restrict__ p, T* __restrict__ r,
+                                                      const T* __restrict__ w,
+                                                      const T* __restrict__ dinv,
+                                                      double* __restrict__ part,
+                                                      const CgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  const T a = (T)sc->alpha, mw = (T)sc->mean_w;
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(g, nf) {
+    x[g] = x[g] + a * p[g];
+    const T rg = r[g] - a * (w[g] - mw);
+    r[g] = rg;
+    const double rd = (double)rg;
+    v[0] += rd * rd;
+    if (JAC) v[1] += rd * rd * (double)dinv[g];
+  }
+  block_partials<2>(v, part);
+}
+
+// convergence bookkeeping after the x, r update; Jacobi: also beta = rz / rho
+template <bool JAC>
+__global__ __launch_bounds__(kVecBlock) void k_after_update(const double* __restrict__ part,
+                                                            int nblk, CgScalars* __restrict__ sc,
+                                                            double* __restrict__ hist,
+                                                            double* __restrict__ ahist,
+                                                            double* __restrict__ bhist) {
+  if (sc->done) return;
+  double S[2];
+  block_total<2>(part, nblk, S);
+  if (threadIdx.x == 0) {
+    const double rr = S[0];
+    const int it = sc->it + 1;
+    sc->it = it;
+    sc->rr = rr;
+    if (hist) hist[it] = sqrt(rr);
+    if (ahist) ahist[it - 1] = sc->alpha;
+    if (!finite(rr)) {
+      sc->status = 3;
+      sc->done = 1;
+    } else if (!sc->fixed && rr <= sc->tol2) {
+      sc->status = 1;
+      sc->done = 1;
+    } else if (it >= sc->max_it) {
+      sc->done = 1;
+    }
+    if (JAC) {
+      const double rz = S[1];
+      const double beta = rz / sc->rho;
+      sc->beta = beta;
+      sc->rho = rz;
+      if (bhist) bhist[it - 1] = beta;
+    }
+  }
+}
+
+// flexible (Polak-Ribiere) beta from z.r and z.(w - mean_w) of the preconditioner pass:
+// beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha z.(w - mean_w) / rho_k
+__global__ __launch_bounds__(kVecBlock) void k_beta_flex(const double* __restrict__ part, int nblk,
+                                                         CgScalars* __restrict__ sc,
+                                                         double* __restrict__ bhist) {
+  if (sc->done) return;
+  double S[2];
+  block_total<2>(part, nblk, S);
+  if (threadIdx.x == 0) {
+    const double rz = S[0], zw = S[1];
+    const double beta = -sc->alpha * zw / sc->rho;
+    sc->beta = beta;
+    sc->rho = rz;
+    if (bhist) bhist[sc->it - 1] = beta;
+    if (!finite(rz) || !finite(beta)) {
+      sc->status = 3;
+      sc->done = 1;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __restrict__ p,
+                                                           const T* __restrict__ r,
+                                                           const T* __restrict__ dinv,
+                                                           const CgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  const T b = (T)sc->beta;
+  GRID_STRIDE(g, nf) p[g] = dinv[g] * r[g] + b * p[g];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_pupdate_z(int64_t nf, T* __restrict__ p,
+                                                         const T* __restrict__ z,
+                                                         const CgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  const T b = (T)sc->beta;
+  GRID_STRIDE(g, nf) p[g] = z[g] + b * p[g];
+}
+
+// ----------------------------------------------------- init / misc kernels
+
+// r = b - R Q^T w_L; partials of r.r and sum(r)
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_residual(int64_t nf, const int32_t* __restrict__ seg,
+                                                        const int32_t* __restrict__ perm,
+                                                        const T* __restrict__ wL,
+                                                        const T* __restrict__ b, T* __restrict__ r,
+                                                        double* __restrict__ part) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(g, nf) {
+    const int32_t a = seg[g], e = seg[g + 1];
+    T s = T(0);
+    for (int32_t q = a; q < e; ++q) s += wL[perm[q]];
+    const T rg = b[g] - s;
+    r[g] = rg;
+    v[0] += (double)rg * (double)rg;
+    v[1] += (double)rg;
+  }
+  block_partials<2>(v, part);
+}
+
+// partials of a.b, a.a, sum(a) (b may be null -> a.a twice)
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_dots(int64_t nf, const T* __restrict__ a,
+                                                    const T* __restrict__ b,
+                                                    double* __restrict__ part) {
+  double v[3] = {0.0, 0.0, 0.0};
+  GRID_STRIDE(g, nf) {
+    const double ag = (double)a[g];
+    const double bg = b ? (double)b[g] : ag;
+    v[0] += ag * bg;
+    v[1] += ag * ag;
+    v[2] += ag;
+  }
+  block_partials<3>(v, part);
+}
+
+template <int NV>
+__global__ __launch_bounds__(kVecBlock) void k_totals(const double* __restrict__ part, int nblk,
+                                                      double* __restrict__ out) {
+  double S[NV];
+  block_total<NV>(part, nblk, S);
+  if (threadIdx.x < NV) out[threadIdx.x] = S[threadIdx.x];
+}
+
+// p = S r (Jacobi) or p = z; partials of r.p
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_init_p(int64_t nf, T* __restrict__ p,
+                                                      const T* __restrict__ r,
+                                                      const T* __restrict__ dinv,
+                                                      const T* __restrict__ z,
+                                                      double* __restrict__ part) {
+  double v[1] = {0.0};
+  GRID_STRIDE(g, nf) {
+    const T pg = z ? z[g] : dinv[g] * r[g];
+    p[g] = pg;
+    v[0] += (double)pg * (double)r[g];
+  }
+  block_partials<1>(v, part);
+}
+
+template <typename T>
+__global__ void k_shift(int64_t n, T* __restrict__ a, double s) {
+  GRID_STRIDE(g, n) a[g] = (T)((double)a[g] - s);
+}
+
+template <typename T>
+__global__ void k_copy(int64_t n, const T* __restrict__ a, T* __restrict__ b) {
+  GRID_STRIDE(g, n) b[g] = a[g];
+}
+
+// r32 = float((r64 - shift) * scale)
+__global__ void k_ir_prepare(int64_t n, const double* __restrict__ r, float* __restrict__ r32,
+                             double shift, double scale) {
+  GRID_STRIDE(g, n) r32[g] = (float)((r[g] - shift) * scale);
+}
+
+// x64 += s * e32
+__global__ void k_ir_update(int64_t n, double* __restrict__ x, const float* __restrict__ e,
+                            double s) {
+  GRID_STRIDE(g, n) x[g] += s * (double)e[g];
+}
+
+// --------------------------------------------------------- Chebyshev kernels
+
+// d = c0 S r; r_k = r; z = d;  optional partials of z.r and z.(w - mean_w)
+template <typename Tr, typename Tp>
+__global__ __launch_bounds__(kVecBlock) void k_cheb_init(int64_t nf, const Tr* __restrict__ r,
+                                                         const Tp* __restrict__ dinv,
+                                                         Tp* __restrict__ d, Tp* __restrict__ rk,
+                                                         Tr* __restrict__ z, double c0, int dots,
+                                                         const Tr* __restrict__ wcg,
+                                                         double* __restrict__ part,
+                                                         const CgScalars* __restrict__ sc) {
+  if (sc && sc->done) return;
+  const double mw = sc ? sc->mean_w : 0.0;
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(g, nf) {
+    const Tp rg = (Tp)r[g];
+    const Tp dg = (Tp)c0 * dinv[g] * rg;
+    d[g] = dg;
+    rk[g] = rg;
+    z[g] = (Tr)dg;
+    if (dots) {
+      v[0] += (double)dg * (double)r[g];
+      v[1] += (double)dg * ((double)wcg[g] - mw);
+    }
+  }
+  if (dots) block_partials<2>(v, part);
+}
+
+// r_k -= R Q^T w_L;  d = a d + b S r_k;  z += d;  optional dots as above
+template <typename Tp, typename Tr>
+__global__ __launch_bounds__(kVecBlock) void k_cheb_step(
+    int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
+    const Tp* __restrict__ wL, Tp* __restrict__ rk, Tp* __restrict__ d,
+    const Tp* __restrict__ dinv, Tr* __restrict__ z, double ca, double cb, int dots,
+    const Tr* __restrict__ rcg, const Tr* __restrict__ wcg, double* __restrict__ part,
+    const CgScalars* __restrict__ sc) {
+  if (sc && sc->done) return;
+  const double mw = sc ? sc->mean_w : 0.0;
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(g, nf) {
+    const int32_t a = seg[g], e = seg[g + 1];
+    Tp s = Tp(0);
+    for (int32_t q = a; q < e; ++q) s += wL[perm[q]];
+    const Tp rkg = rk[g] - s;
+    const Tp dg = (Tp)ca * d[g] + (Tp)cb * dinv[g] * rkg;
+    rk[g] = rkg;
+    d[g] = dg;
+    const Tr zg = z[g] + (Tr)dg;
+    z[g] = zg;
+    if (dots) {
+      v[0] += (double)zg * (double)rcg[g];
+      v[1] += (double)zg * ((double)wcg[g] - mw);
+    }
+  }
+  if (dots) block_partials<2>(v, part);
+}
+
+inline unsigned vgrid(int64_t n) {
+  int64_t b = (n + kVecBlock - 1) / kVecBlock;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, kReduceBlocks));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ SolveWork
+
+SolveWork::~SolveWork() {
+  if (h_sc) (void)hipHostFree(h_sc);
+  if (h_red) (void)hipHostFree(h_red);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
+sem_status SolveWork::init(const sem_mesh* m, int max_iter) {
+  const int64_t nf = std::max<int64_t>(m->n_free, 1);
+  if (!h_sc) SEM_HIP(hipHostMalloc((void**)&h_sc, 4 * sizeof(CgScalars)));
+  if (!h_red) SEM_HIP(hipHostMalloc((void**)&h_red, 64 * sizeof(double)));
+  sem_status st;
+  if ((st = part.ensure(kReduceBlocks * kMaxReduce * sizeof(double)))) return st;
+  if ((st = sc.ensure(sizeof(CgScalars)))) return st;
+  if ((st = red.ensure(64 * sizeof(double)))) return st;
+  const size_t hb = (size_t)(max_iter + 2) * sizeof(double);
+  if ((st = hist.ensure(hb)) || (st = ahist.ensure(hb)) || (st = bhist.ensure(hb))) return st;
+  (void)nf;
+  return SEM_OK;
+}
+
+template <typename T>
+T* SolveWork::vec(DevBuf& b, int64_t n) {
+  if (b.ensure((size_t)std::max<int64_t>(n, 1) * sizeof(T)) != SEM_OK) return nullptr;
+  return b.as<T>();
+}
+template double* SolveWork::vec<double>(DevBuf&, int64_t);
+template float* SolveWork::vec<float>(DevBuf&, int64_t);
+
+// ----------------------------------------------------- small host helpers
+
+template <typename T>
+static sem_status reduce_dots(const sem_mesh* m, SolveWork& W, const T* a, const T* b, double out[3],
+                              hipStream_t s) {
+  const int64_t nf = m->n_free;
+  const unsigned nb = vgrid(nf);
+  hipLaunchKernelGGL((k_dots<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, a, b, W.part.as<double>());
+  hipLaunchKernelGGL((k_totals<3>), dim3(1), dim3(kVecBlock), 0, s, W.part.as<double>(), (int)nb,
+                     W.red.as<double>());
+  SEM_CHECK_LAUNCH("dot products");
+  SEM_HIP(hipMemcpyAsync(W.h_red, W.red.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < 3; ++i) out[i] = W.h_red[i];
+  return SEM_OK;
+}
+
+template <typename T>
+static sem_status remove_mean(const sem_mesh* m, SolveWork& W, T* a, hipStream_t s) {
+  double d[3];
+  sem_status st = reduce_dots<T>(m, W, a, nullptr, d, s);
+  if (st) return st;
+  const double mean = d[2] / (double)m->n_free;
+  hipLaunchKernelGGL((k_shift<T>), dim3(vgrid(m->n_free)), dim3(kVecBlock), 0, s, m->n_free, a, mean);
+  SEM_CHECK_LAUNCH("mean removal");
+  return SEM_OK;
+}
+
+// ----------------------------------------------------------- the operator
+
+template <typename T>
+sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* xf, T* wL,
+                    hipStream_t s, bool timed) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    if (W.ev_used + 2 > (int)W.ev.size()) {
+      hipEvent_t a, b;
+      SEM_HIP(hipEventCreate(&a));
+      SEM_HIP(hipEventCreate(&b));
+      W.ev.push_back(a);
+      W.ev.push_back(b);
+    }
+    e0 = W.ev[W.ev_used];
+    e1 = W.ev[W.ev_used + 1];
+    W.ev_used += 2;
+    SEM_HIP(hipEventRecord(e0, s));
+  }
+  hipError_t e =
+      launch_ax<T>(m, xf, m->lmap.as<int32_t>(), wL, op.k, op.h2, op.G, op.B, op.D, s, op.skip);
+  if (e != hipSuccess) return hip_fail(e, "operator kernel");
+  if (timed) SEM_HIP(hipEventRecord(e1, s));
+  return SEM_OK;
+}
+template sem_status apply_op<double>(const sem_mesh*, SolveWork&, const Op<double>&, const double*,
+                                     double*, hipStream_t, bool);
+template sem_status apply_op<float>(const sem_mesh*, SolveWork&, const Op<float>&, const float*,
+                                    float*, hipStream_t, bool);
+
+// ------------------------------------------------------ Chebyshev on device
+
+template <typename Tr, typename Tp>
+sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
+                          const Tr* r, Tr* z, int order, double lmax, const CgScalars* sc,
+                          const Tr* wcg, double* part, hipStream_t s, int* applies) {
+  const int64_t nf = m->n_free;
+  const unsigned nb = vgrid(nf);
+  Tp* d = W.vec<Tp>(sizeof(Tp) == 8 ? W.cd : W.cd32, nf);
+  Tp* rk = W.vec<Tp>(sizeof(Tp) == 8 ? W.crk : W.crk32, nf);
+  Tp* wL = W.vec<Tp>(sizeof(Tp) == 8 ? W.wL : W.wL32, m->nL);
+  if (!d || !rk || !wL) return fail(SEM_ENOMEM, "Chebyshev work space");
+  const int dots = (sc != nullptr && wcg != nullptr) ? 1 : 0;
+  const double c0 = 4.0 / (3.0 * lmax);
+  Op<Tp> opk = op;
+  if (sc) opk.skip = &sc->done;
+  hipLaunchKernelGGL((k_cheb_init<Tr, Tp>), dim3(nb), dim3(kVecBlock), 0, s, nf, r, dinv, d, rk, z, c0,
+                     (order == 1) ? dots : 0, wcg, part, sc);
+  SEM_CHECK_LAUNCH("Chebyshev init");
+  for (int k = 1; k < order; ++k) {
+    sem_status st = apply_op<Tp>(m, W, opk, d, wL, s, false);
+    if (st) return st;
+    if (applies) ++*applies;
+    const double ca = (2.0 * k - 1.0) / (2.0 * k + 3.0);
+    const double cb = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
+    hipLaunchKernelGGL((k_cheb_step<Tp, Tr>), dim3(nb), dim3(kVecBlock), 0, s, nf,
+                       m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
+                       (k == order - 1) ? dots : 0, r, wcg, part, sc);
+    SEM_CHECK_LAUNCH("Chebyshev step");
+  }
+  return SEM_OK;
+}
+template sem_status cheb_apply_dev<double, double>(const sem_mesh*, SolveWork&, const Op<double>&,
+                                                   const double*, const double*, double*, int,
+                                                   double, const CgScalars*, const double*,
+                                                   double*, hipStream_t, int*);
+template sem_status cheb_apply_dev<double, float>(const sem_mesh*, SolveWork&, const Op<float>&,
+                                                  const float*, const double*, double*, int, double,
+                                                  const CgScalars*, const double*, double*,
+                                                  hipStream_t, int*);
+template sem_status cheb_apply_dev<float, float>(const sem_mesh*, SolveWork&, const Op<float>&,
+                                                 const float*, const float*, float*, int, double,
+                                                 const CgScalars*, const float*, double*,
+                                                 hipStream_t, int*);
+
+// ------------------------------------------------------------------- CG
+
+template <typename T, typename Tp>
+sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgResult& res,
+                    hipStream_t s) {
+  const int64_t nf = m->n_free;
+  const unsigned nb = vgrid(nf);
+  const bool jac = (a.precond == SEM_PRECOND_JACOBI);
+  double* part = W.part.as<double>();
+  CgScalars* sc = W.sc.as<CgScalars>();
+  sem_status st;
+  res = CgResult();
+
+  T* x = a.x;
+  T* r = a.r;
+  T* p = a.p;
+  T* w = a.w;
+  T* z = a.z;
+  T* wL = a.wL;
+
+  // r = b - A x0 (or b)
+  if (a.x_zero) {
+    SEM_HIP(launch_fill<T>(x, nf, T(0), s));
+    hipLaunchKernelGGL((k_copy<T>), dim3(vgrid(nf)), dim3(kVecBlock), 0, s, nf, a.b, r);
+    SEM_CHECK_LAUNCH("copy");
+  } else {
+    if ((st = apply_op<T>(m, W, a.op, x, wL, s, a.profile))) return st;
+    res.applies++;
+    hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
+                       m->fperm.as<int32_t>(), wL, a.b, r, part);
+    SEM_CHECK_LAUNCH("residual");
+  }
+  double bd[3], rd[3];
+  if ((st = reduce_dots<T>(m, W, a.b, nullptr, bd, s))) return st;
+  if ((st = reduce_dots<T>(m, W, r, nullptr, rd, s))) return st;
+  const double bb = bd[0], rr0 = rd[0];
+  res.bnorm = std::sqrt(bb);
+  res.rnorm = std::sqrt(rr0);
+  if (a.hist) a.hist[0] = res.rnorm;
+  if (bb == 0.0 || !std::isfinite(bb)) {
+    if (!std::isfinite(bb)) return fail(SEM_EINVAL, "right-hand side is not finite");
+    SEM_HIP(launch_fill<T>(x, nf, T(0), s));
+    res.converged = true;
+    return SEM_OK;
+  }
+  const double tol2 = a.rtol * a.rtol * bb;
+  if (!a.fixed && rr0 <= tol2) {
+    res.converged = true;
+    return SEM_OK;
+  }
+
+  // z0 = M r0, p0 = z0, rho = r0.z0
+  if (jac) {
+    hipLaunchKernelGGL((k_init_p<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv,
+                       (const T*)nullptr, part);
+  } else {
+    if ((st = a.cheb(m, W, r, z, nullptr, nullptr, part, s, &res.applies))) return st;
+    hipLaunchKernelGGL((k_init_p<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv, z, part);
+  }
+  hipLaunchKernelGGL((k_totals<1>), dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, W.red.as<double>());
+  SEM_CHECK_LAUNCH("initial direction");
+  SEM_HIP(hipMemcpyAsync(W.h_red, W.red.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  const double rho0 = W.h_red[0];
+  if (!(rho0 > 0.0) || !std::isfinite(rho0)) {
+    res.status = 2;
+    return SEM_OK;
+  }
+
+  CgScalars h{};
+  h.rho = rho0;
+  h.bb = bb;
+  h.tol2 = tol2;
+  h.rr = rr0;
+  h.inv_n = 1.0 / (double)nf;
+  h.it = 0;
+  h.done = 0;
+  h.status = 0;
+  h.max_it = a.max_it;
+  h.fixed = a.fixed ? 1 : 0;
+  h.neumann = a.neumann ? 1 : 0;
+  h.flexible = jac ? 0 : 1;
+  W.h_sc[3] = h;
+  SEM_HIP(hipMemcpyAsync(sc, &W.h_sc[3], sizeof(CgScalars), hipMemcpyHostToDevice, s));
+
+  double* hist = W.hist.as<double>();
+  double* ahist = W.ahist.as<double>();
+  double* bhist = W.bhist.as<double>();
+
+  Op<T> op_it = a.op;
+  op_it.skip = &sc->done;
+  auto iteration = [&]() -> sem_status {
+    sem_status e;
+    if ((e = apply_op<T>(m, W, op_it, p, wL, s, a.profile))) return e;
+    hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
+                       m->fperm.as<int32_t>(), wL, p, w, part, sc);
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, sc);
+    if (jac) {
+      hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w,
+                         a.dinv, part, sc);
+      hipLaunchKernelGGL((k_after_update<true>), dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, sc,
+                         hist, ahist, bhist);
+      hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv, sc);
+    } else {
+      hipLaunchKernelGGL((k_update<T, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w,
+                         a.dinv, part, sc);
+      hipLaunchKernelGGL((k_after_update<false>), dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, sc,
+                         hist, ahist, bhist);
+      if ((e = a.cheb(m, W, r, z, sc, w, part, s, nullptr))) return e;
+      hipLaunchKernelGGL(k_beta_flex, dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, sc, bhist);
+      hipLaunchKernelGGL((k_pupdate_z<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, z, sc);
+    }
+    SEM_CHECK_LAUNCH("CG iteration");
+    return SEM_OK;
+  };
+
+  int enq = 0;
+  if (a.fixed) {
+    for (; enq < a.max_it; ++enq)
+      if ((st = iteration())) return st;
+    SEM_HIP(hipMemcpyAsync(&W.h_sc[0], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    h = W.h_sc[0];
+  } else {
+    // keep one chunk queued ahead of the one being polled
+    int chunk = a.check_every;
+    if (chunk <= 0) chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, 2000000 / std::max<int64_t>(nf, 1)));
+    hipEvent_t evs[2];
+    SEM_HIP(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
+    SEM_HIP(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
+    int slot = 0;
+    bool have_prev = false;
+    bool finished = false;
+    while (!finished) {
+      const int n_now = std::min(chunk, a.max_it - enq);
+      for (int c = 0; c < n_now; ++c)
+        if ((st = iteration())) break;
+      enq += n_now;
+      if (st) break;
+      SEM_HIP(hipMemcpyAsync(&W.h_sc[slot], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+      SEM_HIP(hipEventRecord(evs[slot], s));
+      if (have_prev || enq >= a.max_it) {
+        const int ps = (enq >= a.max_it) ? slot : 1 - slot;
+        SEM_HIP(hipEventSynchronize(evs[ps]));
+        if (W.h_sc[ps].done || enq >= a.max_it) {
+          if (enq >= a.max_it) SEM_HIP(hipEventSynchronize(evs[slot]));
+          finished = true;
+        }
+      }
+      have_prev = true;
+      slot = 1 - slot;
+    }
+    SEM_HIP(hipStreamSynchronize(s));
+    (void)hipEventDestroy(evs[0]);
+    (void)hipEventDestroy(evs[1]);
+    if (st) return st;
+    SEM_HIP(hipMemcpy(&W.h_sc[0], sc, sizeof(CgScalars), hipMemcpyDeviceToHost));
+    h = W.h_sc[0];
+  }
+  res.iters = h.it;
+  res.applies += h.it + (jac ? 0 : h.it * (a.cheb_order - 1));
+  res.rnorm = std::sqrt(h.rr);
+  res.status = h.status;
+  res.converged = (h.status == 1) || (a.fixed && h.rr <= tol2);
+  if (a.hist && h.it > 0)
+    SEM_HIP(hipMemcpy(a.hist + 1, hist + 1, h.it * sizeof(double), hipMemcpyDeviceToHost));
+  if (a.alpha_out && h.it > 0) {
+    a.alpha_out->resize(h.it);
+    a.beta_out->resize(h.it);
+    SEM_HIP(hipMemcpy(a.alpha_out->data(), ahist, h.it * sizeof(double), hipMemcpyDeviceToHost));
+    SEM_HIP(hipMemcpy(a.beta_out->data(), bhist, h.it * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return SEM_OK;
+}
+template sem_status cg_solve<double, double>(const sem_mesh*, SolveWork&, const CgArgs<double, double>&,
+                                             CgResult&, hipStream_t);
+template sem_status cg_solve<double, float>(const sem_mesh*, SolveWork&, const CgArgs<double, float>&,
+                                            CgResult&, hipStream_t);
+template sem_status cg_solve<float, float>(const sem_mesh*, SolveWork&, const CgArgs<float, float>&,
+                                           CgResult&, hipStream_t);
+
+// ----------------------------------------------------- exported helpers
+
+sem_status free_remove_mean_f64(const sem_mesh* m, SolveWork& W, double* a, hipStream_t s) {
+  return remove_mean<double>(m, W, a, s);
+}
+sem_status free_dots_f64(const sem_mesh* m, SolveWork& W, const double* a, const double* b,
+                         double out[3], hipStream_t s) {
+  return reduce_dots<double>(m, W, a, b, out, s);
+}
+
+sem_status ir_residual(const sem_mesh* m, SolveWork& W, const Op<double>& op, const double* x,
+                       const double* b, double* r, double out[2], hipStream_t s, bool timed) {
+  double* wL = W.vec<double>(W.wL, m->nL);
+  if (!wL) return fail(SEM_ENOMEM, "work space");
+  sem_status st = apply_op<double>(m, W, op, x, wL, s, timed);
+  if (st) return st;
+  const unsigned nb = vgrid(m->n_free);
+  hipLaunchKernelGGL((k_residual<double>), dim3(nb), dim3(kVecBlock), 0, s, m->n_free,
+                     m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, b, r, W.part.as<double>());
+  hipLaunchKernelGGL((k_totals<2>), dim3(1), dim3(kVecBlock), 0, s, W.part.as<double>(), (int)nb,
+                     W.red.as<double>());
+  SEM_CHECK_LAUNCH("residual");
+  SEM_HIP(hipMemcpyAsync(W.h_red, W.red.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  out[0] = W.h_red[0];
+  out[1] = W.h_red[1];
+  return SEM_OK;
+}
+
+sem_status ir_prepare(const sem_mesh* m, const double* r, float* r32, double shift, double scale,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_prepare, dim3(vgrid(m->n_free)), dim3(kVecBlock), 0, s, m->n_free, r, r32,
+                     shift, scale);
+  SEM_CHECK_LAUNCH("refinement prepare");
+  return SEM_OK;
+}
+
+sem_status ir_update(const sem_mesh* m, double* x, const float* e, double sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_update, dim3(vgrid(m->n_free)), dim3(kVecBlock), 0, s, m->n_free, x, e, sc);
+  SEM_CHECK_LAUNCH("refinement update");
+  return SEM_OK;
+}
+
+}  // namespace sem

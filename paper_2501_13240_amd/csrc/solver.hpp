@@ -1,0 +1,94 @@
+// Internal interface of the solver drivers.
+#pragma once
+
+#include <functional>
+#include <vector>
+
+#include "common.hpp"
+
+namespace sem {
+
+// Per-mesh work space of the solve entry points (grown on demand, kept until
+// sem_free_mesh).
+struct SolveWork {
+  DevBuf bf, x, r, p, w, z, wL, dinv, tmpf;          // FP64
+  DevBuf x32, r32, ri32, p32, w32, z32, wL32, dinv32, k32; // FP32
+  DevBuf cd, crk, cd32, crk32;                       // Chebyshev d and r_k
+  DevBuf part, sc, red, hist, ahist, bhist;
+  CgScalars* h_sc = nullptr;  // pinned: [0..1] polling slots, [3] upload
+  double* h_red = nullptr;    // pinned reduction results
+  std::vector<hipEvent_t> ev; // profiling events
+  int ev_used = 0;
+  ~SolveWork();
+  sem_status init(const sem_mesh* m, int max_iter);
+  template <typename T> T* vec(DevBuf& b, int64_t n);
+};
+
+// operator data in one precision
+template <typename T>
+struct Op {
+  const T* G = nullptr;
+  const T* B = nullptr;
+  const T* k = nullptr;
+  const T* D = nullptr;
+  T h2 = T(0);
+  const int32_t* skip = nullptr;  // device flag: nonzero = skip the launch's work
+};
+
+struct CgResult {
+  int iters = 0;
+  int applies = 0;
+  int status = 0;  // 0 running/limit, 1 converged, 2 breakdown, 3 non-finite
+  bool converged = false;
+  double bnorm = 0.0, rnorm = 0.0;
+};
+
+template <typename T>
+using ChebFn = std::function<sem_status(const sem_mesh*, SolveWork&, const T* r, T* z,
+                                        const CgScalars* sc, const T* wcg, double* part,
+                                        hipStream_t s, int* applies)>;
+
+template <typename T, typename Tp>
+struct CgArgs {
+  Op<T> op;
+  const T* b = nullptr;  // free rhs
+  T *x = nullptr, *r = nullptr, *p = nullptr, *w = nullptr, *z = nullptr, *wL = nullptr;
+  const T* dinv = nullptr;
+  int precond = SEM_PRECOND_JACOBI;
+  int cheb_order = 3;
+  ChebFn<T> cheb;
+  double rtol = 1e-10;
+  int max_it = 1000;
+  bool fixed = false;
+  bool x_zero = true;
+  bool neumann = false;
+  bool profile = false;
+  int check_every = 0;
+  double* hist = nullptr;                      // host, max_it + 1
+  std::vector<double>* alpha_out = nullptr;    // CG coefficients (Lanczos)
+  std::vector<double>* beta_out = nullptr;
+};
+
+template <typename T>
+sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* xf, T* wL,
+                    hipStream_t s, bool timed);
+
+template <typename Tr, typename Tp>
+sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
+                          const Tr* r, Tr* z, int order, double lmax, const CgScalars* sc,
+                          const Tr* wcg, double* part, hipStream_t s, int* applies);
+
+template <typename T, typename Tp>
+sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgResult& res,
+                    hipStream_t s);
+
+sem_status free_remove_mean_f64(const sem_mesh* m, SolveWork& W, double* a, hipStream_t s);
+sem_status free_dots_f64(const sem_mesh* m, SolveWork& W, const double* a, const double* b,
+                         double out[3], hipStream_t s);
+sem_status ir_residual(const sem_mesh* m, SolveWork& W, const Op<double>& op, const double* x,
+                       const double* b, double* r, double out[2], hipStream_t s, bool timed);
+sem_status ir_prepare(const sem_mesh* m, const double* r, float* r32, double shift, double scale,
+                      hipStream_t s);
+sem_status ir_update(const sem_mesh* m, double* x, const float* e, double sc, hipStream_t s);
+
+}  // namespace sem

@@ -1,0 +1,276 @@
+"""GPU parity of libsem against the CPU oracle (element by element).
+
+Tolerances (FP64 unless stated):
+  geometry G, B                        <= 1e-12 relative (per array, 2-norm)
+  element operator w = A_L u           <= 1e-12 relative (2-norm)
+  gather-scatter, mask                 <= 1e-14 relative (at most 8 addends, other order)
+  Jacobi inverse                       <= 1e-12 relative
+  Chebyshev preconditioner (FP64)      <= 1e-12 relative
+  FP32 operator / preconditioner       stated, asserted <= 2e-5 relative
+Meshes are seeded (sem_inputs) and sized so the oracle runs in seconds while
+spanning several workgroups and a ragged tail of elements.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.geometry import geometric_factors
+from oracle.operator import local_apply, kgrad_contraction
+from sem_inputs import box_mesh, config_mesh, random_local_normal
+
+pytestmark = pytest.mark.gpu
+
+sem = pytest.importorskip("paper_2501_13240_amd")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def small_mesh(N, shape=(3, 2, 3), dirichlet="all", deform=True, periodic=(False, False, False)):
+    return box_mesh(N, shape, (1.0, 1.5, 1.0), periodic=periodic, dirichlet=dirichlet,
+                    jitter=0.05, deform=dict(a=0.15, seed=3, kind="walls") if deform else None)
+
+
+@pytest.mark.parametrize("N", list(range(1, 11)))
+def test_geometry_matches_oracle(N):
+    m = small_mesh(N)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    G, B = M.geometry()
+    Go, Bo, _ = geometric_factors(m.xyz, N)
+    assert rel(G.cpu().numpy(), Go) <= 1e-12
+    assert rel(B.cpu().numpy(), Bo) <= 1e-12
+
+
+@pytest.mark.parametrize("N", list(range(1, 11)))
+@pytest.mark.parametrize("with_k", [False, True])
+def test_ax_fp64_and_fp32_match_oracle(N, with_k):
+    m = small_mesh(N)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    Go, Bo, _ = geometric_factors(m.xyz, N)
+    u = random_local_normal((m.E, m.P), 100 + N)
+    k = np.exp(0.5 * random_local_normal((m.E, m.P), 200 + N)) if with_k else None
+    h2 = 0.7 if with_k else 0.0
+    w_or = local_apply(u, Go, Bo, N, k=k, h2=h2)
+    w = sem.ax(M, dev(u), k=None if k is None else dev(k), h2=h2).cpu().numpy()
+    e64 = rel(w, w_or)
+    assert e64 <= 1e-12, e64
+    w32 = sem.ax(M, dev(u, torch.float32), k=None if k is None else dev(k, torch.float32),
+                 h2=h2).cpu().numpy()
+    e32 = rel(w32, w_or)
+    print(f"N={N} k={with_k}: fp64 rel err {e64:.2e}, fp32 rel err {e32:.2e}")
+    assert e32 <= 2e-5
+
+
+def test_ax_config1_full_and_constants():
+    m, _ = config_mesh(1)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    Go, Bo, _ = geometric_factors(m.xyz, m.N)
+    u = random_local_normal((m.E, m.P), 7)
+    assert rel(sem.ax(M, dev(u)).cpu().numpy(), local_apply(u, Go, Bo, m.N)) <= 1e-12
+    w1 = sem.ax(M, torch.ones(m.E, m.P, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert np.abs(w1).max() <= 1e-12 * np.abs(Go).max()
+    mass = sem.mass(M, dev(u)).cpu().numpy()
+    assert rel(mass, Bo * u) <= 1e-15
+
+
+@pytest.mark.parametrize("periodic,dirichlet", [((False, False, False), "all"),
+                                                ((True, True, False), "z"),
+                                                ((False, False, False), "none")])
+def test_gs_and_mask_match_oracle(periodic, dirichlet):
+    N = 5
+    m = box_mesh(N, (3, 4, 3), (4.0, 4.0, 1.0), periodic=periodic, dirichlet=dirichlet,
+                 z_ratio=20.0)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    num = oracle.Numbering(m.gid, m.dirichlet)
+    v = random_local_normal((m.E, m.P), 11)
+    out = sem.gs(M, dev(v)).cpu().numpy()
+    assert rel(out, num.gs(v)) <= 1e-14
+    out32 = sem.gs(M, dev(v, torch.float32)).cpu().numpy()
+    assert rel(out32, num.gs(v)) <= 1e-6
+    msk = sem.mask(M, dev(v)).cpu().numpy()
+    np.testing.assert_array_equal(msk, num.mask(v))
+    info = M.info
+    assert info["n_unique"] == num.n and info["n_free"] == num.n_free
+    assert info["has_nullspace"] == (1 if dirichlet == "none" else 0)
+
+
+@pytest.mark.parametrize("with_k", [False, True])
+def test_jacobi_inverse_matches_oracle(with_k):
+    N = 6
+    m = small_mesh(N)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    k = np.exp(0.5 * random_local_normal((m.E, m.P), 5)) if with_k else None
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, N, k=k, h2=0.3 if with_k else 0.0)
+    d = sem.jacobi_inverse(M, k=None if k is None else dev(k), h2=P.h2).cpu().numpy()
+    ref = P.num.to_local(1.0 / P.diag())
+    assert rel(d, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 5])
+def test_chebyshev_apply_matches_oracle(order):
+    m, _ = config_mesh(1, N=5)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    rf = np.random.default_rng(order).standard_normal(P.num.n_free)
+    lmax = 2.3
+    z_or = oracle.chebyshev_apply(P.apply, 1.0 / P.diag(), rf, order, lmax)
+    z = sem.cheb_apply(M, dev(P.num.to_local(rf)), lmax, order=order).cpu().numpy()
+    assert rel(z, P.num.to_local(z_or)) <= 1e-12
+    z32 = sem.cheb_apply(M, dev(P.num.to_local(rf)), lmax, order=order, prec="fp32").cpu().numpy()
+    e32 = rel(z32, P.num.to_local(z_or))
+    print(f"order {order}: fp32 Chebyshev rel err {e32:.2e}")
+    assert e32 <= 2e-5
+
+
+def test_lmax_estimate_brackets_true_value():
+    N = 4
+    m = small_mesh(N, shape=(3, 3, 3))
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, N)
+    A = oracle.explicit_matrix(P.G, P.B, N, P.num).toarray()
+    d = np.diag(A)
+    import scipy.linalg as sla
+    true = sla.eigh(A, np.diag(d), eigvals_only=True)[-1]
+    est = sem.lmax_estimate(M)
+    assert 0.95 * true <= est <= true * (1 + 1e-10), (est, true)
+    est_or = oracle.lanczos_lmax(P.apply, 1.0 / d, np.random.default_rng(1).standard_normal(d.size))
+    assert abs(est - est_or) <= 0.05 * true
+
+
+def _true_rel_residual(P, x_local, b_free):
+    xf = P.num.from_local_consistent(x_local)
+    r = b_free - P.apply(xf)
+    return np.linalg.norm(r) / np.linalg.norm(b_free), xf
+
+
+def test_pcg_config1_jacobi_matches_oracle():
+    m, fld = config_mesh(1)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    f = fld["f"] * 3 * np.pi ** 2
+    b_or = P.rhs_from_source(f)
+    ref = P.solve(b_or, rtol=1e-10)
+    bL = sem.gs(M, sem.mass(M, dev(f)))
+    x, st = sem.solve(M, bL, rtol=1e-10, history=True)
+    res, xf = _true_rel_residual(P, x.cpu().numpy(), b_or)
+    print(f"config 1: iters gpu {st['iters']} oracle {ref['iters']}, true rel res {res:.2e}, "
+          f"x err vs oracle {rel(xf, ref['x']):.2e}")
+    assert st["converged"] == 1 and res <= 1.2e-10
+    assert abs(st["iters"] - ref["iters"]) <= 2
+    assert rel(xf, ref["x"]) <= 1e-8
+    n = min(len(st["history"]), len(ref["res_hist"]))
+    np.testing.assert_allclose(st["history"][:n], ref["res_hist"][:n], rtol=1e-6)
+    # Dirichlet copies are returned as exact zeros; copies agree
+    xl = x.cpu().numpy()
+    assert np.all(xl[m.dirichlet.astype(bool)] == 0.0)
+    assert np.abs(P.num.gs(xl) / P.num.mult[P.num.lid] - xl).max() <= 1e-15 * np.abs(xl).max()
+
+
+def test_pcg_fixed_iterations_periodic_box_histories_agree():
+    m, fld = config_mesh(2, shape=(6, 6, 4))
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    b_or = P.num.from_local_consistent(fld["b"])
+    ref = P.solve(b_or, rtol=1e-30, max_iter=100, fixed_iters=True)
+    x, st = sem.solve(M, dev(fld["b"]), max_iter=100, fixed_iters=True, history=True)
+    assert st["iters"] == 100
+    np.testing.assert_allclose(st["history"], ref["res_hist"], rtol=1e-8)
+    assert rel(P.num.from_local_consistent(x.cpu().numpy()), ref["x"]) <= 1e-8
+
+
+def test_pcg_neumann_matches_oracle():
+    m, fld = config_mesh(5, N=4, shape=(4, 4, 4))
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    b_or = P.num.from_local_consistent(fld["b"])
+    ref = P.solve(b_or, rtol=1e-10)
+    x, st = sem.solve(M, dev(fld["b"]), rtol=1e-10)
+    xf = P.num.from_local_consistent(x.cpu().numpy())
+    assert abs(xf.mean()) <= 1e-13 * np.abs(xf).max()
+    r = b_or - b_or.mean() - P.apply(xf)
+    print(f"neumann: iters gpu {st['iters']} oracle {ref['iters']}")
+    assert np.linalg.norm(r) <= 1.2e-10 * np.linalg.norm(b_or - b_or.mean())
+    assert rel(xf, ref["x"]) <= 1e-7
+
+
+@pytest.mark.parametrize("precond_prec", ["fp64", "fp32"])
+def test_pcg_chebyshev_reaches_tolerance(precond_prec):
+    m, fld = config_mesh(1)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    f = fld["f"] * 3 * np.pi ** 2
+    b_or = P.rhs_from_source(f)
+    bL = sem.gs(M, sem.mass(M, dev(f)))
+    x, st = sem.solve(M, bL, precond="chebyshev", precond_prec=precond_prec, rtol=1e-10)
+    res, xf = _true_rel_residual(P, x.cpu().numpy(), b_or)
+    ref = P.solve(b_or, rtol=1e-10, precond="chebyshev", rho_hat=st["lmax"])
+    print(f"chebyshev {precond_prec}: iters gpu {st['iters']} oracle {ref['iters']} res {res:.2e}")
+    assert res <= 1.2e-10
+    assert abs(st["iters"] - ref["iters"]) <= 3
+    assert rel(xf, ref["x"]) <= 1e-8
+
+
+@pytest.mark.parametrize("cfg,N", [(1, 7), (3, 9)])
+@pytest.mark.parametrize("precond", ["jacobi", "chebyshev"])
+def test_mixed_ir_reaches_fp64_tolerance(cfg, N, precond):
+    m, fld = config_mesh(cfg, N=N)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    f = fld["f"] * 3 * np.pi ** 2
+    b_or = P.rhs_from_source(f)
+    ref = P.solve(b_or, rtol=1e-12)
+    bL = sem.gs(M, sem.mass(M, dev(f)))
+    x, st = sem.solve(M, bL, mode="mixed_ir", precond=precond, precond_prec="fp32", rtol=1e-10)
+    res, xf = _true_rel_residual(P, x.cpu().numpy(), b_or)
+    print(f"mixed cfg{cfg} N={N} {precond}: outer {st['outer_iters']} inner {st['iters']} "
+          f"true rel res {res:.2e} err vs oracle {rel(xf, ref['x']):.2e}")
+    assert st["converged"] == 1 and res <= 1.2e-10
+    assert rel(xf, ref["x"]) <= 1e-7
+
+
+def test_ax_backward_matches_oracle():
+    N = 5
+    m = small_mesh(N)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    Go, Bo, _ = geometric_factors(m.xyz, N)
+    u = random_local_normal((m.E, m.P), 1)
+    wb = random_local_normal((m.E, m.P), 2)
+    k = np.exp(0.5 * random_local_normal((m.E, m.P), 3))
+    ub, kb = sem.ax_backward(M, dev(u), dev(wb), k=dev(k), h2=0.4)
+    assert rel(ub.cpu().numpy(), local_apply(wb, Go, Bo, N, k=k, h2=0.4)) <= 1e-12
+    assert rel(kb.cpu().numpy(), kgrad_contraction(u, wb, Go, N)) <= 1e-12
+
+
+def test_solve_is_bit_reproducible():
+    m, fld = config_mesh(2, shape=(4, 4, 4))
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    b = dev(fld["b"])
+    x1, s1 = sem.solve(M, b, max_iter=50, fixed_iters=True)
+    x2, s2 = sem.solve(M, b, max_iter=50, fixed_iters=True)
+    assert torch.equal(x1, x2)
+
+
+def test_solve_errors_are_reported():
+    m, fld = config_mesh(1, N=3)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    b = dev(fld["f"])
+    with pytest.raises(sem.SemError, match="ENOCONV"):
+        sem.solve(M, b, rtol=1e-14, max_iter=3)
+    x, st = sem.solve(M, b, rtol=1e-14, max_iter=3, raise_on_noconv=False)
+    assert st["iters"] == 3 and st["converged"] == 0
+    bad = b.clone()
+    bad[0, 5] = float("nan")
+    with pytest.raises(sem.SemError):
+        sem.solve(M, bad)
+    # warm start: resume from the returned iterate and reach the tolerance
+    x2, st2 = sem.solve(M, b, x0=x, rtol=1e-10)
+    assert st2["converged"] == 1

@@ -1,0 +1,162 @@
+"""Host-side checks of libsem (no device work): exported symbols, the
+library's GLL quadrature, its numbering, and argument validation that fails
+before any device call."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2501_13240_amd as sem
+from paper_2501_13240_amd import _lib as L
+from sem_inputs import box_mesh, config_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(sem_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    declared = _declared_symbols()
+    assert len(declared) >= 17
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(L.SIGNATURES) == declared
+
+
+def test_struct_layouts_match_header():
+    # field offsets a C compiler gives these structs on x86-64
+    assert ctypes.sizeof(L.MeshDesc) == 40
+    assert ctypes.sizeof(L.SolveOpts) == 72
+    assert ctypes.sizeof(L.SolveStats) == 56
+    assert ctypes.sizeof(L.MeshInfo) == 48
+
+
+CLOSED = {
+    1: ([-1.0, 1.0], [1.0, 1.0]),
+    2: ([-1.0, 0.0, 1.0], [1 / 3, 4 / 3, 1 / 3]),
+    3: ([-1.0, -1 / np.sqrt(5), 1 / np.sqrt(5), 1.0], [1 / 6, 5 / 6, 5 / 6, 1 / 6]),
+    4: ([-1.0, -np.sqrt(3 / 7), 0.0, np.sqrt(3 / 7), 1.0],
+        [1 / 10, 49 / 90, 32 / 45, 49 / 90, 1 / 10]),
+}
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_library_gll_closed_forms(N):
+    xi, rho, D = sem.gll(N)
+    np.testing.assert_allclose(xi, CLOSED[N][0], atol=1e-15)
+    np.testing.assert_allclose(rho, CLOSED[N][1], rtol=1e-14)
+
+
+@pytest.mark.parametrize("N", range(1, 11))
+def test_library_gll_exactness(N):
+    xi, rho, D = sem.gll(N)
+    for m in range(2 * N):
+        assert abs(rho @ xi ** m - (0.0 if m % 2 else 2.0 / (m + 1))) < 1e-13
+    for m in range(N + 1):
+        d = m * xi ** (m - 1) if m else 0 * xi
+        np.testing.assert_allclose(D @ xi ** m, d, atol=1e-12 * N * N)
+
+
+@pytest.mark.parametrize("N", [0, 11, -3])
+def test_library_gll_rejects_bad_order(N):
+    assert L.load().sem_gll(N, None, None, None) == L.SEM_EINVAL
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_numbering_counts_and_first_touch(cfg):
+    m, _ = config_mesh(cfg)
+    fi, nu, nf, ns = sem.host_numbering(m.N, m.gid, m.dirichlet)
+    assert nu == (4 * m.N + 1) ** 3 and nf == (4 * m.N - 1) ** 3
+    # copies of one global node share one free index; Dirichlet copies get -1
+    d = m.dirichlet.astype(bool)
+    assert np.all(fi[d] == -1) and np.all(fi[~d] >= 0)
+    first = {}
+    for g, f in zip(m.gid.ravel(), fi.ravel()):
+        if f >= 0:
+            assert first.setdefault(g, f) == f
+    # first-touch order: free indices appear in increasing order of first visit
+    seen = fi.ravel()[fi.ravel() >= 0]
+    _, idx = np.unique(seen, return_index=True)
+    assert np.all(np.diff(np.sort(idx)) > 0)
+    assert np.all(seen[np.sort(idx)] == np.arange(nf))
+
+
+def test_numbering_periodic_and_shared_counts():
+    N = 3
+    m = box_mesh(N, (4, 3, 2), (4.0, 4.0, 1.0), periodic=(True, True, False), dirichlet="z")
+    fi, nu, nf, ns = sem.host_numbering(N, m.gid, m.dirichlet)
+    assert nu == 12 * 9 * 7 and nf == 12 * 9 * 5
+    mult = np.bincount(m.gid.ravel())
+    assert ns == np.sum(mult > 1)
+
+
+def test_numbering_sparse_gids_use_sort_path():
+    m = box_mesh(2, (2, 2, 2), dirichlet="none")
+    gid = m.gid * 1_000_003 + 7  # far beyond the direct-table range
+    fi, nu, nf, ns = sem.host_numbering(2, gid, None)
+    fi2, nu2, nf2, ns2 = sem.host_numbering(2, m.gid, None)
+    assert (nu, nf, ns) == (nu2, nf2, ns2)
+    np.testing.assert_array_equal(fi, fi2)
+
+
+def test_numbering_rejects_inconsistent_dirichlet_and_negative_gid():
+    m = box_mesh(2, (2, 2, 2))
+    d = m.dirichlet.copy()
+    # flag one copy of an interior shared node only
+    g = m.gid[0, -1]
+    idx = np.argwhere(m.gid == g)
+    d[tuple(idx[0])] = 1
+    with pytest.raises(sem.SemError, match="EINVAL"):
+        sem.host_numbering(2, m.gid, d)
+    with pytest.raises(sem.SemError, match="EINVAL"):
+        sem.host_numbering(2, m.gid - 1, None)
+
+
+def _setup_status(N, E, xyz, gid, d):
+    lib = L.load()
+    desc = L.MeshDesc(N, E, None if xyz is None else xyz.ctypes.data_as(ctypes.c_void_p),
+                      None if gid is None else gid.ctypes.data_as(ctypes.c_void_p),
+                      None if d is None else d.ctypes.data_as(ctypes.c_void_p))
+    h = ctypes.c_void_p()
+    return lib.sem_setup_mesh(ctypes.byref(desc), None, ctypes.byref(h)), lib.sem_last_error()
+
+
+def test_setup_validation_fails_before_device_work():
+    m = box_mesh(2, (2, 2, 2))
+    xyz, gid, d = m.xyz.copy(), m.gid.copy(), m.dirichlet.copy()
+    assert _setup_status(0, m.E, xyz, gid, d)[0] == L.SEM_EINVAL
+    assert _setup_status(11, m.E, xyz, gid, d)[0] == L.SEM_EINVAL
+    assert _setup_status(2, 0, xyz, gid, d)[0] == L.SEM_EINVAL
+    assert _setup_status(2, m.E, None, gid, d)[0] == L.SEM_EINVAL
+    bad = xyz.copy()
+    bad[3, 5, 1] = np.nan
+    st, msg = _setup_status(2, m.E, bad, gid, d)
+    assert st == L.SEM_EINVAL and b"finite" in msg
+    d2 = d.copy()
+    g = gid[0, -1]
+    d2[tuple(np.argwhere(gid == g)[0])] = 1
+    st, msg = _setup_status(2, m.E, xyz, gid, d2)
+    assert st == L.SEM_EINVAL and b"Dirichlet" in msg
+
+
+def test_null_handles_are_rejected():
+    lib = L.load()
+    assert lib.sem_ax(None, None, None, None, 0.0, 0, None) == L.SEM_EINVAL
+    assert lib.sem_gs(None, None, 0, None) == L.SEM_EINVAL
+    assert lib.sem_pcg_solve(None, None, None, None, 0.0, None, None, None) == L.SEM_EINVAL
+    assert lib.sem_free_mesh(None) == L.SEM_OK
+    opts = L.SolveOpts()
+    lib.sem_solve_opts_default(ctypes.byref(opts))
+    assert opts.rtol == 1e-10 and opts.cheb_order == 3 and opts.max_iter == 10000
