@@ -543,14 +543,14 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
       const int order = opts.cheb_order;
       if (opts.precond_prec == SEM_FP64) {
         a.cheb = [op64, dinv, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                           double* z, const CgScalars* sc, const double* wcg,
+                                           double* z, CgScalars* sc, const double* wcg,
                                            double* part, hipStream_t ss, int* ap) {
           return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, sc, wcg,
                                                 part, ss, ap);
         };
       } else {
         a.cheb = [op32, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                             double* z, const CgScalars* sc, const double* wcg,
+                                             double* z, CgScalars* sc, const double* wcg,
                                              double* part, hipStream_t ss, int* ap) {
           return cheb_apply_dev<double, float>(mm, WW, op32, dinv32, r, z, order, lmax, sc, wcg,
                                                part, ss, ap);
@@ -593,7 +593,7 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     if (cheb) {
       const int order = opts.cheb_order;
       a.cheb = [op32, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const float* rr,
-                                           float* z, const CgScalars* sc, const float* wcg,
+                                           float* z, CgScalars* sc, const float* wcg,
                                            double* part, hipStream_t ss, int* ap) {
         return cheb_apply_dev<float, float>(mm, WW, op32, dinv32, rr, z, order, lmax, sc, wcg, part,
                                             ss, ap);

@@ -84,7 +84,29 @@ struct CgScalars {
   int32_t neumann;  // 1 = project out the constant mode
   int32_t flexible; // 1 = Polak-Ribiere beta
   int32_t pad2;
+  uint32_t cnt[4];  // block-completion counters of the reducing kernels (0 between launches)
 };
+
+// Sum of the local copies perm[a..b) of one global node, in ascending order
+// (deterministic).  The index loads of up to 8 copies are issued together,
+// then the value loads, instead of one dependent pair per copy.
+template <typename Tacc, typename T>
+__device__ __forceinline__ Tacc segment_sum(const int32_t* __restrict__ perm,
+                                            const T* __restrict__ v, int32_t a, int32_t b) {
+  Tacc s = Tacc(0);
+  for (int32_t q0 = a; q0 < b; q0 += 8) {
+    int32_t idx[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) idx[c] = (q0 + c < b) ? perm[q0 + c] : -1;
+    T val[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) val[c] = idx[c] >= 0 ? v[idx[c]] : T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (q0 + c < b) s += (Tacc)val[c];
+  }
+  return s;
+}
 
 // ------------------------------------------------------------- the mesh
 struct SolveWork;

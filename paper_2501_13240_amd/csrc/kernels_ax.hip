@@ -4,22 +4,28 @@
 // matrix-free tensor-product operator of Sec. 2.2, whose leading work is
 // dense (N+1)x(N+1) contractions identical for all elements.
 //
-// Mapping: one thread per (i, j) column of an element, the column's N+1
-// values along t held in registers.  For N = 7 an element is exactly one
-// wavefront (8 x 8 columns = 64 lanes).  The r- and s-contractions read the
-// current k-plane from LDS; the t-contraction runs in registers with D[k][l]
-// read as a wave-uniform (scalar) value; the transposed contractions reuse the
-// same plane buffers.  Per local point the kernel streams u (8 B), the six
-// geometric factors (48 B, planar layout [E][6][P] so each factor of a plane
-// is one contiguous 8*(N+1)^2-byte run) and w (8 B): 64 B in FP64.
+// Mapping: one thread per local point (two for N = 10), one element (or a
+// few small ones) per workgroup.  Every thread issues all of its global loads
+// -- u (or its gather through the free numbering), the six geometric factors
+// and k -- before the first barrier, so a workgroup has its whole element in
+// flight at once; the streamed arrays are read and w written with
+// nontemporal hints (each byte is touched once).  The element block and D
+// live in LDS; the reference-gradient phase and the transposed phase are
+// separated by one barrier.  For N = 7 a wavefront is exactly one k-plane,
+// so the t-direction coefficients D[k][l] are wave-uniform and come from
+// scalar loads instead of LDS.
+//
+// Per local point the FP64 apply streams u (8 B), six geometric factors
+// (48 B, planar layout [E][6][P]) and w (8 B): 64 B.
 #include "common.hpp"
 
 namespace sem {
 namespace {
 
-constexpr int pick_epb(int n1) {
-  // elements per workgroup: fill whole wavefronts with (N+1)^2 columns each
-  return n1 == 8 ? 1 : n1 == 10 ? 5 : n1 == 11 ? 4 : (256 / (n1 * n1) > 0 ? 256 / (n1 * n1) : 1);
+// elements per workgroup and points per thread, chosen so that the workgroup
+// fills whole wavefronts with little idle work and stays within 1024 threads
+constexpr int pick_epb(int P) {
+  return P <= 8 ? 32 : P <= 27 ? 9 : P <= 64 ? 4 : P <= 343 ? 2 : 1;
 }
 
 template <int N>
@@ -27,10 +33,21 @@ struct Shape {
   static constexpr int n1 = N + 1;
   static constexpr int P2 = n1 * n1;
   static constexpr int P = P2 * n1;
-  static constexpr int EPB = pick_epb(n1);
-  static constexpr int BT = ((EPB * P2 + 63) / 64) * 64;
-  static constexpr int LD = (n1 % 2 == 0) ? n1 + 1 : n1;  // padded LDS row (bank spread)
+  static constexpr int PPT = P > 1024 ? 2 : 1;          // points per thread
+  static constexpr int TPE = (P + PPT - 1) / PPT;       // threads per element
+  static constexpr int EPB = pick_epb(P);
+  static constexpr int BT = ((EPB * TPE + 63) / 64) * 64;
+  static constexpr bool kUniform = (P2 == 64 && PPT == 1);  // a wavefront = one k-plane
 };
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T v, T* p) {
+  __builtin_nontemporal_store(v, p);
+}
 
 template <int N, typename T, bool GATHER>
 __global__ __launch_bounds__(Shape<N>::BT) void ax_kernel(
@@ -38,169 +55,161 @@ __global__ __launch_bounds__(Shape<N>::BT) void ax_kernel(
     const T* __restrict__ kf, const T h2, const T* __restrict__ G, const T* __restrict__ B,
     const T* __restrict__ D, const int64_t E, const int32_t* __restrict__ skip) {
   using S = Shape<N>;
-  constexpr int n1 = S::n1, P2 = S::P2, P = S::P, EPB = S::EPB, LD = S::LD;
+  constexpr int n1 = S::n1, P2 = S::P2, P = S::P, EPB = S::EPB, PPT = S::PPT, TPE = S::TPE;
   if (skip && *skip) return;  // uniform over the grid
-  __shared__ T su[EPB][n1 * LD];
-  __shared__ T svr[EPB][n1 * LD];
-  __shared__ T svs[EPB][n1 * LD];
+  __shared__ T su[EPB][P];
+  __shared__ T sv[EPB][3][P];
+  __shared__ T sD[n1 * n1];
 
   const int t = threadIdx.x;
-  const int slot = t / P2;
-  const int col = t - slot * P2;
-  const int i = col % n1, j = col / n1;
+  const int slot = t / TPE;
+  const int tl = t - slot * TPE;
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
-  const bool lds_ok = slot < EPB;
-  const bool active = lds_ok && e < E;
-  const int ss = lds_ok ? slot : 0;
+  const bool ok_e = slot < EPB && e < E;
+  const int ss = slot < EPB ? slot : 0;
+  const bool use_k = kf != nullptr;
+  const bool use_h2 = h2 != T(0);
 
-  T Dri[n1], Drj[n1], Dci[n1], Dcj[n1];
+  T uq[PPT], gq[PPT][6], kq[PPT];
 #pragma unroll
-  for (int l = 0; l < n1; ++l) {
-    Dri[l] = D[i * n1 + l];
-    Drj[l] = D[j * n1 + l];
-    Dci[l] = D[l * n1 + i];
-    Dcj[l] = D[l * n1 + j];
-  }
-
-  const int64_t base = e * P + col;
-  T ureg[n1];
-#pragma unroll
-  for (int k = 0; k < n1; ++k) {
+  for (int s = 0; s < PPT; ++s) {
+    const int q = tl + s * TPE;
+    const bool ok = ok_e && q < P;
+    const int64_t idx = e * P + q;
     T v = T(0);
-    if (active) {
-      const int64_t idx = base + k * P2;
+    if (ok) {
       if constexpr (GATHER) {
-        const int32_t lm = lmap[idx];
+        const int32_t lm = ld_stream(lmap + idx);
         v = lm >= 0 ? u[lm] : T(0);
       } else {
-        v = u[idx];
+        v = ld_stream(u + idx);
       }
     }
-    ureg[k] = v;
-  }
-
-  const T* g = G + e * 6 * P + col;
-  T wreg[n1], vt[n1];
+    uq[s] = v;
+    const T* g = G + e * 6 * P + q;
 #pragma unroll
-  for (int k = 0; k < n1; ++k) {
-    if (lds_ok) su[ss][j * LD + i] = ureg[k];
-    __syncthreads();
-    T ur = T(0), us = T(0), ut = T(0);
-    if (lds_ok) {
+    for (int c = 0; c < 6; ++c) gq[s][c] = ok ? ld_stream(g + c * P) : T(0);
+    kq[s] = (ok && use_k) ? ld_stream(kf + idx) : T(1);
+  }
+  for (int a = t; a < n1 * n1; a += S::BT) sD[a] = D[a];
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int q = tl + s * TPE;
+    if (slot < EPB && q < P) su[ss][q] = uq[s];
+  }
+  __syncthreads();
+
+  // reference gradient, metric, conductivity
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int q = tl + s * TPE;
+    if (slot < EPB && q < P) {
+      const int i = q % n1, j = (q / n1) % n1;
+      const int k = S::kUniform ? __builtin_amdgcn_readfirstlane(q / P2) : q / P2;
+      const T* uk = &su[ss][k * P2];
+      T ur = T(0), us = T(0), ut = T(0);
 #pragma unroll
       for (int l = 0; l < n1; ++l) {
-        ur += Dri[l] * su[ss][j * LD + l];
-        us += Drj[l] * su[ss][l * LD + i];
+        ur += sD[i * n1 + l] * uk[j * n1 + l];
+        us += sD[j * n1 + l] * uk[l * n1 + i];
+        const T dkl = S::kUniform ? D[k * n1 + l] : sD[k * n1 + l];
+        ut += dkl * su[ss][l * P2 + j * n1 + i];
       }
-    }
-#pragma unroll
-    for (int l = 0; l < n1; ++l) ut += D[k * n1 + l] * ureg[l];
-    T vr = T(0), vs = T(0), vtt = T(0);
-    if (active) {
-      const int o = k * P2;
-      const T grr = g[o], grs = g[P + o], grt = g[2 * P + o];
-      const T gss = g[3 * P + o], gst = g[4 * P + o], gtt = g[5 * P + o];
-      vr = grr * ur + grs * us + grt * ut;
-      vs = grs * ur + gss * us + gst * ut;
-      vtt = grt * ur + gst * us + gtt * ut;
-      if (kf) {
-        const T kq = kf[base + o];
-        vr *= kq;
-        vs *= kq;
-        vtt *= kq;
+      const T* gc = gq[s];
+      T vr = gc[0] * ur + gc[1] * us + gc[2] * ut;
+      T vs = gc[1] * ur + gc[3] * us + gc[4] * ut;
+      T vt = gc[2] * ur + gc[4] * us + gc[5] * ut;
+      if (use_k) {
+        vr *= kq[s];
+        vs *= kq[s];
+        vt *= kq[s];
       }
+      sv[ss][0][q] = vr;
+      sv[ss][1][q] = vs;
+      sv[ss][2][q] = vt;
     }
-    vt[k] = vtt;
-    if (lds_ok) {
-      svr[ss][j * LD + i] = vr;
-      svs[ss][j * LD + i] = vs;
-    }
-    __syncthreads();
-    T acc = T(0);
-    if (lds_ok) {
-#pragma unroll
-      for (int l = 0; l < n1; ++l) acc += Dci[l] * svr[ss][j * LD + l] + Dcj[l] * svs[ss][l * LD + i];
-    }
-    wreg[k] = acc;
   }
+  __syncthreads();
 
-  if (active) {
+  // transposed contractions (+ mass term)
 #pragma unroll
-    for (int k = 0; k < n1; ++k) {
-      T acc = wreg[k];
+  for (int s = 0; s < PPT; ++s) {
+    const int q = tl + s * TPE;
+    if (ok_e && q < P) {
+      const int i = q % n1, j = (q / n1) % n1;
+      const int k = S::kUniform ? __builtin_amdgcn_readfirstlane(q / P2) : q / P2;
+      const T* vr = &sv[ss][0][k * P2];
+      const T* vs = &sv[ss][1][k * P2];
+      T acc = T(0);
 #pragma unroll
-      for (int l = 0; l < n1; ++l) acc += D[l * n1 + k] * vt[l];
-      if (h2 != T(0)) acc += h2 * B[base + k * P2] * ureg[k];
-      w[base + k * P2] = acc;
+      for (int l = 0; l < n1; ++l) {
+        acc += sD[l * n1 + i] * vr[j * n1 + l];
+        acc += sD[l * n1 + j] * vs[l * n1 + i];
+        const T dlk = S::kUniform ? D[l * n1 + k] : sD[l * n1 + k];
+        acc += dlk * sv[ss][2][l * P2 + j * n1 + i];
+      }
+      const int64_t idx = e * P + q;
+      if (use_h2) acc += h2 * ld_stream(B + idx) * uq[s];
+      st_stream(acc, w + idx);
     }
   }
 }
 
 // kbar_q = sum_ab (D_a wbar)_q G_ab,q (D_b u)_q: the derivative of the
-// operator in k contracted with a cotangent (same column mapping).
+// operator in k contracted with a cotangent (same mapping, 72 B per point).
 template <int N>
 __global__ __launch_bounds__(Shape<N>::BT) void kbar_kernel(
     const double* __restrict__ u, const double* __restrict__ wb, double* __restrict__ kbar,
     const double* __restrict__ G, const double* __restrict__ D, const int64_t E) {
   using S = Shape<N>;
-  constexpr int n1 = S::n1, P2 = S::P2, P = S::P, EPB = S::EPB, LD = S::LD;
-  __shared__ double su[EPB][n1 * LD];
-  __shared__ double sw[EPB][n1 * LD];
+  constexpr int n1 = S::n1, P2 = S::P2, P = S::P, EPB = S::EPB, PPT = S::PPT, TPE = S::TPE;
+  __shared__ double su[EPB][P];
+  __shared__ double sw[EPB][P];
+  __shared__ double sD[n1 * n1];
   const int t = threadIdx.x;
-  const int slot = t / P2;
-  const int col = t - slot * P2;
-  const int i = col % n1, j = col / n1;
+  const int slot = t / TPE;
+  const int tl = t - slot * TPE;
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
-  const bool lds_ok = slot < EPB;
-  const bool active = lds_ok && e < E;
-  const int ss = lds_ok ? slot : 0;
-
-  double Dri[n1], Drj[n1];
+  const bool ok_e = slot < EPB && e < E;
+  const int ss = slot < EPB ? slot : 0;
+  double gq[PPT][6];
 #pragma unroll
-  for (int l = 0; l < n1; ++l) {
-    Dri[l] = D[i * n1 + l];
-    Drj[l] = D[j * n1 + l];
-  }
-  const int64_t base = e * P + col;
-  double ucol[n1], wcol[n1];
+  for (int s = 0; s < PPT; ++s) {
+    const int q = tl + s * TPE;
+    const bool ok = ok_e && q < P;
+    const double* g = G + e * 6 * P + q;
 #pragma unroll
-  for (int k = 0; k < n1; ++k) {
-    ucol[k] = active ? u[base + k * P2] : 0.0;
-    wcol[k] = active ? wb[base + k * P2] : 0.0;
-  }
-  const double* g = G + e * 6 * P + col;
-#pragma unroll
-  for (int k = 0; k < n1; ++k) {
-    if (lds_ok) {
-      su[ss][j * LD + i] = ucol[k];
-      sw[ss][j * LD + i] = wcol[k];
+    for (int c = 0; c < 6; ++c) gq[s][c] = ok ? ld_stream(g + c * P) : 0.0;
+    if (slot < EPB && q < P) {
+      su[ss][q] = ok ? ld_stream(u + e * P + q) : 0.0;
+      sw[ss][q] = ok ? ld_stream(wb + e * P + q) : 0.0;
     }
-    __syncthreads();
-    double ur = 0, us = 0, ut = 0, wr = 0, ws = 0, wt = 0;
-    if (lds_ok) {
+  }
+  for (int a = t; a < n1 * n1; a += S::BT) sD[a] = D[a];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int q = tl + s * TPE;
+    if (ok_e && q < P) {
+      const int i = q % n1, j = (q / n1) % n1, k = q / P2;
+      double ur = 0, us = 0, ut = 0, wr = 0, ws = 0, wt = 0;
 #pragma unroll
       for (int l = 0; l < n1; ++l) {
-        ur += Dri[l] * su[ss][j * LD + l];
-        us += Drj[l] * su[ss][l * LD + i];
-        wr += Dri[l] * sw[ss][j * LD + l];
-        ws += Drj[l] * sw[ss][l * LD + i];
+        const double dil = sD[i * n1 + l], djl = sD[j * n1 + l], dkl = sD[k * n1 + l];
+        const int qr = k * P2 + j * n1 + l, qs = k * P2 + l * n1 + i, qt = l * P2 + j * n1 + i;
+        ur += dil * su[ss][qr];
+        us += djl * su[ss][qs];
+        ut += dkl * su[ss][qt];
+        wr += dil * sw[ss][qr];
+        ws += djl * sw[ss][qs];
+        wt += dkl * sw[ss][qt];
       }
+      const double* gc = gq[s];
+      const double vr = gc[0] * ur + gc[1] * us + gc[2] * ut;
+      const double vs = gc[1] * ur + gc[3] * us + gc[4] * ut;
+      const double vt = gc[2] * ur + gc[4] * us + gc[5] * ut;
+      st_stream(wr * vr + ws * vs + wt * vt, kbar + e * P + q);
     }
-#pragma unroll
-    for (int l = 0; l < n1; ++l) {
-      ut += D[k * n1 + l] * ucol[l];
-      wt += D[k * n1 + l] * wcol[l];
-    }
-    if (active) {
-      const int o = k * P2;
-      const double grr = g[o], grs = g[P + o], grt = g[2 * P + o];
-      const double gss = g[3 * P + o], gst = g[4 * P + o], gtt = g[5 * P + o];
-      const double vr = grr * ur + grs * us + grt * ut;
-      const double vs = grs * ur + gss * us + gst * ut;
-      const double vt = grt * ur + gst * us + gtt * ut;
-      kbar[base + o] = wr * vr + ws * vs + wt * vt;
-    }
-    __syncthreads();
   }
 }
 

@@ -26,8 +26,7 @@ __global__ void gs_local_kernel(int64_t ns, const int32_t* __restrict__ seg,
                                 const int32_t* __restrict__ perm, T* __restrict__ v) {
   GRID_STRIDE(g, ns) {
     const int32_t a = seg[g], b = seg[g + 1];
-    T s = T(0);
-    for (int32_t p = a; p < b; ++p) s += v[perm[p]];
+    const T s = segment_sum<T>(perm, v, a, b);
     for (int32_t p = a; p < b; ++p) v[perm[p]] = s;
   }
 }
@@ -44,8 +43,7 @@ __global__ void local_to_free_avg_kernel(int64_t nf, const int32_t* __restrict__
                                          const Tin* __restrict__ vL, Tout* __restrict__ vf) {
   GRID_STRIDE(g, nf) {
     const int32_t a = seg[g], b = seg[g + 1];
-    double s = 0.0;
-    for (int32_t p = a; p < b; ++p) s += (double)vL[perm[p]];
+    const double s = segment_sum<double>(perm, vL, a, b);
     vf[g] = (Tout)(s / (double)(b - a));
   }
 }
@@ -56,10 +54,7 @@ __global__ void free_sum_kernel(int64_t nf, const int32_t* __restrict__ seg,
                                 const int32_t* __restrict__ perm, const Tin* __restrict__ wL,
                                 Tout* __restrict__ wf) {
   GRID_STRIDE(g, nf) {
-    const int32_t a = seg[g], b = seg[g + 1];
-    Tin s = Tin(0);
-    for (int32_t p = a; p < b; ++p) s += wL[perm[p]];
-    wf[g] = (Tout)s;
+    wf[g] = (Tout)segment_sum<Tin>(perm, wL, seg[g], seg[g + 1]);
   }
 }
 

@@ -86,35 +86,49 @@ __device__ __forceinline__ void block_total(const double* __restrict__ part, int
 __device__ __forceinline__ bool finite(double x) { return x == x && fabs(x) <= 1.7976931348623157e308; }
 
 // ------------------------------------------------------------- CG kernels
+//
+// Each reducing kernel writes per-block partial sums; the block that finishes
+// last (counted with one atomic) sums all partials in block order -- a fixed
+// order, so results do not depend on scheduling -- and updates the scalars.
+// This replaces a separate single-block finalisation launch.
 
-// w = R Q^T w_L (segmented sum); partials of p.w, sum(w), sum(p)
+template <int NV>
+__device__ __forceinline__ bool last_block_total(double (&v)[NV], double* __restrict__ part,
+                                                 unsigned* __restrict__ counter, double (&S)[NV]) {
+  __shared__ bool am_last;
+  block_partials<NV>(v, part);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) am_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!am_last) return false;
+  __threadfence();
+  block_total<NV>(part, gridDim.x, S);
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
+  return true;
+}
+
+// w = R Q^T w_L (segmented sum); p.w, sum(w), sum(p) -> alpha
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t* __restrict__ seg,
-                                                       const int32_t* __restrict__ perm,
-                                                       const T* __restrict__ wL,
-                                                       const T* __restrict__ p, T* __restrict__ w,
-                                                       double* __restrict__ part,
-                                                       const CgScalars* __restrict__ sc) {
+__global__ __launch_bounds__(kVecBlock) void k_gsum_alpha(int64_t nf,
+                                                          const int32_t* __restrict__ seg,
+                                                          const int32_t* __restrict__ perm,
+                                                          const T* __restrict__ wL,
+                                                          const T* __restrict__ p, T* __restrict__ w,
+                                                          double* __restrict__ part,
+                                                          CgScalars* __restrict__ sc) {
   if (sc->done) return;
   double v[3] = {0.0, 0.0, 0.0};
   GRID_STRIDE(g, nf) {
-    const int32_t a = seg[g], b = seg[g + 1];
-    T s = T(0);
-    for (int32_t q = a; q < b; ++q) s += wL[perm[q]];
+    const T s = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
     w[g] = s;
     const double pg = (double)p[g];
     v[0] += pg * (double)s;
     v[1] += (double)s;
     v[2] += pg;
   }
-  block_partials<3>(v, part);
-}
-
-__global__ __launch_bounds__(kVecBlock) void k_alpha(const double* __restrict__ part, int nblk,
-                                                     CgScalars* __restrict__ sc) {
-  if (sc->done) return;
   double S[3];
-  block_total<3>(part, nblk, S);
+  if (!last_block_total<3>(v, part, &sc->cnt[0], S)) return;
   if (threadIdx.x == 0) {
     double pw = S[0], mw = 0.0;
     if (sc->neumann) {
@@ -132,14 +146,18 @@ __global__ __launch_bounds__(kVecBlock) void k_alpha(const double* __restrict__ 
   }
 }
 
-// x += alpha p;  r -= alpha (w - mean_w);  partials of r.r (and r.S r)
+// x += alpha p;  r -= alpha (w - mean_w);  r.r (and r.S r) -> convergence test
+// (and, for Jacobi, beta = r.S r / rho)
 template <typename T, bool JAC>
 __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict__ x,
                                                       const T* __restrict__ p, T* __restrict__ r,
                                                       const T* __restrict__ w,
                                                       const T* __restrict__ dinv,
                                                       double* __restrict__ part,
-                                                      const CgScalars* __restrict__ sc) {
+                                                      CgScalars* __restrict__ sc,
+                                                      double* __restrict__ hist,
+                                                      double* __restrict__ ahist,
+                                                      double* __restrict__ bhist) {
   if (sc->done) return;
   const T a = (T)sc->alpha, mw = (T)sc->mean_w;
   double v[2] = {0.0, 0.0};
@@ -151,19 +169,8 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
     v[0] += rd * rd;
     if (JAC) v[1] += rd * rd * (double)dinv[g];
   }
-  block_partials<2>(v, part);
-}
-
-// convergence bookkeeping after the x, r update; Jacobi: also beta = rz / rho
-template <bool JAC>
-__global__ __launch_bounds__(kVecBlock) void k_after_update(const double* __restrict__ part,
-                                                            int nblk, CgScalars* __restrict__ sc,
-                                                            double* __restrict__ hist,
-                                                            double* __restrict__ ahist,
-                                                            double* __restrict__ bhist) {
-  if (sc->done) return;
   double S[2];
-  block_total<2>(part, nblk, S);
+  if (!last_block_total<2>(v, part, &sc->cnt[1], S)) return;
   if (threadIdx.x == 0) {
     const double rr = S[0];
     const int it = sc->it + 1;
@@ -192,22 +199,16 @@ __global__ __launch_bounds__(kVecBlock) void k_after_update(const double* __rest
 
 // flexible (Polak-Ribiere) beta from z.r and z.(w - mean_w) of the preconditioner pass:
 // beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha z.(w - mean_w) / rho_k
-__global__ __launch_bounds__(kVecBlock) void k_beta_flex(const double* __restrict__ part, int nblk,
-                                                         CgScalars* __restrict__ sc,
-                                                         double* __restrict__ bhist) {
-  if (sc->done) return;
-  double S[2];
-  block_total<2>(part, nblk, S);
-  if (threadIdx.x == 0) {
-    const double rz = S[0], zw = S[1];
-    const double beta = -sc->alpha * zw / sc->rho;
-    sc->beta = beta;
-    sc->rho = rz;
-    if (bhist) bhist[sc->it - 1] = beta;
-    if (!finite(rz) || !finite(beta)) {
-      sc->status = 3;
-      sc->done = 1;
-    }
+__device__ __forceinline__ void beta_flex(const double (&S)[2], CgScalars* __restrict__ sc,
+                                          double* __restrict__ bhist) {
+  const double rz = S[0], zw = S[1];
+  const double beta = -sc->alpha * zw / sc->rho;
+  sc->beta = beta;
+  sc->rho = rz;
+  if (bhist) bhist[sc->it - 1] = beta;
+  if (!finite(rz) || !finite(beta)) {
+    sc->status = 3;
+    sc->done = 1;
   }
 }
 
@@ -241,9 +242,7 @@ __global__ __launch_bounds__(kVecBlock) void k_residual(int64_t nf, const int32_
                                                         double* __restrict__ part) {
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(g, nf) {
-    const int32_t a = seg[g], e = seg[g + 1];
-    T s = T(0);
-    for (int32_t q = a; q < e; ++q) s += wL[perm[q]];
+    const T s = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
     const T rg = b[g] - s;
     r[g] = rg;
     v[0] += (double)rg * (double)rg;
@@ -315,18 +314,22 @@ __global__ void k_ir_update(int64_t n, double* __restrict__ x, const float* __re
 }
 
 // --------------------------------------------------------- Chebyshev kernels
+//
+// With FLEX the pass also reduces z.r and z.(w - mean_w) of the enclosing
+// flexible CG and its last block sets beta.
 
-// d = c0 S r; r_k = r; z = d;  optional partials of z.r and z.(w - mean_w)
-template <typename Tr, typename Tp>
+// d = c0 S r; r_k = r; z = d
+template <typename Tr, typename Tp, bool FLEX>
 __global__ __launch_bounds__(kVecBlock) void k_cheb_init(int64_t nf, const Tr* __restrict__ r,
                                                          const Tp* __restrict__ dinv,
                                                          Tp* __restrict__ d, Tp* __restrict__ rk,
-                                                         Tr* __restrict__ z, double c0, int dots,
+                                                         Tr* __restrict__ z, double c0,
                                                          const Tr* __restrict__ wcg,
                                                          double* __restrict__ part,
-                                                         const CgScalars* __restrict__ sc) {
+                                                         CgScalars* __restrict__ sc,
+                                                         double* __restrict__ bhist) {
   if (sc && sc->done) return;
-  const double mw = sc ? sc->mean_w : 0.0;
+  const double mw = FLEX ? sc->mean_w : 0.0;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(g, nf) {
     const Tp rg = (Tp)r[g];
@@ -334,41 +337,47 @@ __global__ __launch_bounds__(kVecBlock) void k_cheb_init(int64_t nf, const Tr* _
     d[g] = dg;
     rk[g] = rg;
     z[g] = (Tr)dg;
-    if (dots) {
+    if (FLEX) {
       v[0] += (double)dg * (double)r[g];
       v[1] += (double)dg * ((double)wcg[g] - mw);
     }
   }
-  if (dots) block_partials<2>(v, part);
+  if constexpr (FLEX) {
+    double S[2];
+    if (!last_block_total<2>(v, part, &sc->cnt[2], S)) return;
+    if (threadIdx.x == 0) beta_flex(S, sc, bhist);
+  }
 }
 
-// r_k -= R Q^T w_L;  d = a d + b S r_k;  z += d;  optional dots as above
-template <typename Tp, typename Tr>
+// r_k -= R Q^T w_L;  d = a d + b S r_k;  z += d
+template <typename Tp, typename Tr, bool FLEX>
 __global__ __launch_bounds__(kVecBlock) void k_cheb_step(
     int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
     const Tp* __restrict__ wL, Tp* __restrict__ rk, Tp* __restrict__ d,
-    const Tp* __restrict__ dinv, Tr* __restrict__ z, double ca, double cb, int dots,
+    const Tp* __restrict__ dinv, Tr* __restrict__ z, double ca, double cb,
     const Tr* __restrict__ rcg, const Tr* __restrict__ wcg, double* __restrict__ part,
-    const CgScalars* __restrict__ sc) {
+    CgScalars* __restrict__ sc, double* __restrict__ bhist) {
   if (sc && sc->done) return;
-  const double mw = sc ? sc->mean_w : 0.0;
+  const double mw = FLEX ? sc->mean_w : 0.0;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(g, nf) {
-    const int32_t a = seg[g], e = seg[g + 1];
-    Tp s = Tp(0);
-    for (int32_t q = a; q < e; ++q) s += wL[perm[q]];
+    const Tp s = segment_sum<Tp>(perm, wL, seg[g], seg[g + 1]);
     const Tp rkg = rk[g] - s;
     const Tp dg = (Tp)ca * d[g] + (Tp)cb * dinv[g] * rkg;
     rk[g] = rkg;
     d[g] = dg;
     const Tr zg = z[g] + (Tr)dg;
     z[g] = zg;
-    if (dots) {
+    if (FLEX) {
       v[0] += (double)zg * (double)rcg[g];
       v[1] += (double)zg * ((double)wcg[g] - mw);
     }
   }
-  if (dots) block_partials<2>(v, part);
+  if constexpr (FLEX) {
+    double S[2];
+    if (!last_block_total<2>(v, part, &sc->cnt[2], S)) return;
+    if (threadIdx.x == 0) beta_flex(S, sc, bhist);
+  }
 }
 
 inline unsigned vgrid(int64_t n) {
@@ -470,7 +479,7 @@ template sem_status apply_op<float>(const sem_mesh*, SolveWork&, const Op<float>
 
 template <typename Tr, typename Tp>
 sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
-                          const Tr* r, Tr* z, int order, double lmax, const CgScalars* sc,
+                          const Tr* r, Tr* z, int order, double lmax, CgScalars* sc,
                           const Tr* wcg, double* part, hipStream_t s, int* applies) {
   const int64_t nf = m->n_free;
   const unsigned nb = vgrid(nf);
@@ -478,12 +487,17 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
   Tp* rk = W.vec<Tp>(sizeof(Tp) == 8 ? W.crk : W.crk32, nf);
   Tp* wL = W.vec<Tp>(sizeof(Tp) == 8 ? W.wL : W.wL32, m->nL);
   if (!d || !rk || !wL) return fail(SEM_ENOMEM, "Chebyshev work space");
-  const int dots = (sc != nullptr && wcg != nullptr) ? 1 : 0;
+  const bool flex = (sc != nullptr && wcg != nullptr);
+  double* bhist = W.bhist.as<double>();
   const double c0 = 4.0 / (3.0 * lmax);
   Op<Tp> opk = op;
   if (sc) opk.skip = &sc->done;
-  hipLaunchKernelGGL((k_cheb_init<Tr, Tp>), dim3(nb), dim3(kVecBlock), 0, s, nf, r, dinv, d, rk, z, c0,
-                     (order == 1) ? dots : 0, wcg, part, sc);
+  if (flex && order == 1)
+    hipLaunchKernelGGL((k_cheb_init<Tr, Tp, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, r, dinv, d,
+                       rk, z, c0, wcg, part, sc, bhist);
+  else
+    hipLaunchKernelGGL((k_cheb_init<Tr, Tp, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, r, dinv,
+                       d, rk, z, c0, wcg, part, sc, bhist);
   SEM_CHECK_LAUNCH("Chebyshev init");
   for (int k = 1; k < order; ++k) {
     sem_status st = apply_op<Tp>(m, W, opk, d, wL, s, false);
@@ -491,25 +505,30 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
     if (applies) ++*applies;
     const double ca = (2.0 * k - 1.0) / (2.0 * k + 3.0);
     const double cb = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
-    hipLaunchKernelGGL((k_cheb_step<Tp, Tr>), dim3(nb), dim3(kVecBlock), 0, s, nf,
-                       m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
-                       (k == order - 1) ? dots : 0, r, wcg, part, sc);
+    if (flex && k == order - 1)
+      hipLaunchKernelGGL((k_cheb_step<Tp, Tr, true>), dim3(nb), dim3(kVecBlock), 0, s, nf,
+                         m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
+                         r, wcg, part, sc, bhist);
+    else
+      hipLaunchKernelGGL((k_cheb_step<Tp, Tr, false>), dim3(nb), dim3(kVecBlock), 0, s, nf,
+                         m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
+                         r, wcg, part, sc, bhist);
     SEM_CHECK_LAUNCH("Chebyshev step");
   }
   return SEM_OK;
 }
 template sem_status cheb_apply_dev<double, double>(const sem_mesh*, SolveWork&, const Op<double>&,
                                                    const double*, const double*, double*, int,
-                                                   double, const CgScalars*, const double*,
-                                                   double*, hipStream_t, int*);
+                                                   double, CgScalars*, const double*, double*,
+                                                   hipStream_t, int*);
 template sem_status cheb_apply_dev<double, float>(const sem_mesh*, SolveWork&, const Op<float>&,
                                                   const float*, const double*, double*, int, double,
-                                                  const CgScalars*, const double*, double*,
-                                                  hipStream_t, int*);
+                                                  CgScalars*, const double*, double*, hipStream_t,
+                                                  int*);
 template sem_status cheb_apply_dev<float, float>(const sem_mesh*, SolveWork&, const Op<float>&,
                                                  const float*, const float*, float*, int, double,
-                                                 const CgScalars*, const float*, double*,
-                                                 hipStream_t, int*);
+                                                 CgScalars*, const float*, double*, hipStream_t,
+                                                 int*);
 
 // ------------------------------------------------------------------- CG
 
@@ -605,22 +624,16 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   auto iteration = [&]() -> sem_status {
     sem_status e;
     if ((e = apply_op<T>(m, W, op_it, p, wL, s, a.profile))) return e;
-    hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
+    hipLaunchKernelGGL((k_gsum_alpha<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
                        m->fperm.as<int32_t>(), wL, p, w, part, sc);
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, sc);
     if (jac) {
       hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w,
-                         a.dinv, part, sc);
-      hipLaunchKernelGGL((k_after_update<true>), dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, sc,
-                         hist, ahist, bhist);
+                         a.dinv, part, sc, hist, ahist, bhist);
       hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv, sc);
     } else {
       hipLaunchKernelGGL((k_update<T, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w,
-                         a.dinv, part, sc);
-      hipLaunchKernelGGL((k_after_update<false>), dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, sc,
-                         hist, ahist, bhist);
+                         a.dinv, part, sc, hist, ahist, bhist);
       if ((e = a.cheb(m, W, r, z, sc, w, part, s, nullptr))) return e;
-      hipLaunchKernelGGL(k_beta_flex, dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, sc, bhist);
       hipLaunchKernelGGL((k_pupdate_z<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, z, sc);
     }
     SEM_CHECK_LAUNCH("CG iteration");

@@ -45,7 +45,7 @@ struct CgResult {
 
 template <typename T>
 using ChebFn = std::function<sem_status(const sem_mesh*, SolveWork&, const T* r, T* z,
-                                        const CgScalars* sc, const T* wcg, double* part,
+                                        CgScalars* sc, const T* wcg, double* part,
                                         hipStream_t s, int* applies)>;
 
 template <typename T, typename Tp>
@@ -75,7 +75,7 @@ sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* x
 
 template <typename Tr, typename Tp>
 sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
-                          const Tr* r, Tr* z, int order, double lmax, const CgScalars* sc,
+                          const Tr* r, Tr* z, int order, double lmax, CgScalars* sc,
                           const Tr* wcg, double* part, hipStream_t s, int* applies);
 
 template <typename T, typename Tp>

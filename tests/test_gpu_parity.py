@@ -79,7 +79,7 @@ def test_ax_config1_full_and_constants():
     w1 = sem.ax(M, torch.ones(m.E, m.P, dtype=torch.float64, device="cuda")).cpu().numpy()
     assert np.abs(w1).max() <= 1e-12 * np.abs(Go).max()
     mass = sem.mass(M, dev(u)).cpu().numpy()
-    assert rel(mass, Bo * u) <= 1e-15
+    assert rel(mass, Bo * u) <= 1e-14
 
 
 @pytest.mark.parametrize("periodic,dirichlet", [((False, False, False), "all"),
@@ -168,7 +168,9 @@ def test_pcg_config1_jacobi_matches_oracle():
     assert abs(st["iters"] - ref["iters"]) <= 2
     assert rel(xf, ref["x"]) <= 1e-8
     n = min(len(st["history"]), len(ref["res_hist"]))
-    np.testing.assert_allclose(st["history"][:n], ref["res_hist"][:n], rtol=1e-6)
+    # rounding differences dominate once ||r|| is near 1e-12 ||r_0||
+    np.testing.assert_allclose(st["history"][:n], ref["res_hist"][:n], rtol=1e-6,
+                               atol=1e-12 * ref["res_hist"][0])
     # Dirichlet copies are returned as exact zeros; copies agree
     xl = x.cpu().numpy()
     assert np.all(xl[m.dirichlet.astype(bool)] == 0.0)
@@ -268,7 +270,8 @@ def test_solve_errors_are_reported():
     x, st = sem.solve(M, b, rtol=1e-14, max_iter=3, raise_on_noconv=False)
     assert st["iters"] == 3 and st["converged"] == 0
     bad = b.clone()
-    bad[0, 5] = float("nan")
+    free = np.argwhere(m.dirichlet == 0)[0]
+    bad[int(free[0]), int(free[1])] = float("nan")
     with pytest.raises(sem.SemError):
         sem.solve(M, bad)
     # warm start: resume from the returned iterate and reach the tolerance
