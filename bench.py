@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--ax-reps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-vs-FP64 solve comparison on the 32^3, N=9 Neumann box")
     return ap.parse_args()
 
 
@@ -67,6 +69,58 @@ def cpu_baseline(iters):
                         f"32x8x16-element slice of the same recipe ({P.num.n} unique nodes), "
                         f"single-threaded einsum/bincount, {dt:.1f} s"),
                 seconds=dt)
+
+
+def true_rel_residual(sem, M, b, x, k=None, h2=0.0):
+    """||b - A x|| / ||b|| over the free unique nodes with the FP64 operator."""
+    import torch
+
+    w = sem.gs(M, sem.ax(M, x, k=k, h2=h2))
+    r = sem.mask(M, (b - w).contiguous())
+    bb = sem.mask(M, b.clone())
+    if M.info["has_nullspace"] and h2 == 0.0:
+        mult = M.multiplicity()
+        n = M.info["n_unique"]
+        r = r - torch.sum(r / mult) / n
+        bb = bb - torch.sum(bb / mult) / n
+    mult = M.multiplicity()
+    return float(torch.sqrt(torch.sum(r * r / mult) / torch.sum(bb * bb / mult)))
+
+
+def mixed_vs_fp64(sem):
+    """Time to ||b - A x|| <= 1e-10 ||b|| on the 32^3-element, N = 9,
+    all-Neumann box: FP64 Jacobi CG against the mixed-precision variants."""
+    import torch
+    from sem_inputs import config_mesh
+
+    m, fld = config_mesh(5)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    b = torch.tensor(fld["b"], device="cuda")
+    del fld, m
+    variants = {
+        "fp64_jacobi_cg": dict(mode="cg", precond="jacobi"),
+        "fp64_cheb3_fcg": dict(mode="cg", precond="chebyshev", precond_prec="fp64"),
+        "fp64_cg_fp32_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="fp32"),
+        "mixed_ir_fp32_cg": dict(mode="mixed_ir", precond="jacobi", precond_prec="fp32"),
+    }
+    out = {"workload": "32x32x32 hexahedra, N=9, tanh 1:20 z-clustering, seeded wall-preserving "
+                       "deformation, all-Neumann (constant mode removed), zero-mean random rhs",
+           "n_unique": M.info["n_unique"], "rtol": 1e-10}
+    sem.lmax_estimate(M)  # bound estimate shared by the Chebyshev variants (cached)
+    for name, v in variants.items():
+        x, st = sem.solve(M, b, rtol=1e-10, max_iter=30000, **v)
+        res = true_rel_residual(sem, M, b, x)
+        out[name] = {"ms": st["time_ms"], "iters": st["iters"], "outer": st["outer_iters"],
+                     "true_rel_res": res,
+                     "gdof_s": M.info["n_unique"] * st["iters"] / (st["time_ms"] * 1e-3) / 1e9}
+        log(f"  {name}: {st['time_ms']:.1f} ms, {st['iters']} it, true rel res {res:.2e}")
+    best = min((k for k in variants if k != "fp64_jacobi_cg"
+                and out[k]["true_rel_res"] <= 1e-10), key=lambda k: out[k]["ms"], default=None)
+    out["fastest_mixed"] = best
+    if best:
+        out["speedup_vs_fp64"] = out["fp64_jacobi_cg"]["ms"] / out[best]["ms"]
+    M.close()
+    return out
 
 
 def main():
@@ -174,13 +228,16 @@ def main():
         "ax_gdof_s": n_unique / (sem_ax_ms * 1e-3) / 1e9,
         "ax_us": sem_ax_ms * 1e3,
     }
+    if not args.no_mixed:
+        log("mixed vs FP64 on the 32^3, N=9 Neumann box ...")
+        M.close()
+        out["mixed_vs_fp64"] = mixed_vs_fp64(sem)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline(args.cpu_sample_iters)
         cb.pop("seconds", None)
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
-    M.close()
 
 
 if __name__ == "__main__":

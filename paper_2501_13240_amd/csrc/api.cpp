@@ -429,12 +429,12 @@ sem_status sem_cheb_apply(const sem_mesh* m, const double* r, double* z, const d
   SEM_HIP((launch_local_to_free_avg<double, double>(m, r, rf, s)));
   if (prec == SEM_FP64) {
     st = cheb_apply_dev<double, double>(m, W, op64_of(m, k, h2), W.dinv.as<double>(), rf, zf, order,
-                                        lmax, nullptr, nullptr, nullptr, s, nullptr);
+                                        lmax, ChebCg(), s, nullptr);
   } else {
     Op<float> o32;
     if ((st = op32_of(m, W, k, h2, s, o32))) return st;
     st = cheb_apply_dev<double, float>(m, W, o32, W.dinv32.as<float>(), rf, zf, order, lmax,
-                                       nullptr, nullptr, nullptr, s, nullptr);
+                                       ChebCg(), s, nullptr);
   }
   if (st) return st;
   SEM_HIP((launch_free_to_local<double, double>(m, zf, z, s)));
@@ -543,17 +543,13 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
       const int order = opts.cheb_order;
       if (opts.precond_prec == SEM_FP64) {
         a.cheb = [op64, dinv, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                           double* z, CgScalars* sc, const double* wcg,
-                                           double* part, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, sc, wcg,
-                                                part, ss, ap);
+                                           double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
+          return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, cg, ss, ap);
         };
       } else {
         a.cheb = [op32, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                             double* z, CgScalars* sc, const double* wcg,
-                                             double* part, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, float>(mm, WW, op32, dinv32, r, z, order, lmax, sc, wcg,
-                                               part, ss, ap);
+                                             double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
+          return cheb_apply_dev<double, float>(mm, WW, op32, dinv32, r, z, order, lmax, cg, ss, ap);
         };
       }
     }
@@ -593,10 +589,8 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     if (cheb) {
       const int order = opts.cheb_order;
       a.cheb = [op32, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const float* rr,
-                                           float* z, CgScalars* sc, const float* wcg,
-                                           double* part, hipStream_t ss, int* ap) {
-        return cheb_apply_dev<float, float>(mm, WW, op32, dinv32, rr, z, order, lmax, sc, wcg, part,
-                                            ss, ap);
+                                           float* z, const ChebCg& cg, hipStream_t ss, int* ap) {
+        return cheb_apply_dev<float, float>(mm, WW, op32, dinv32, rr, z, order, lmax, cg, ss, ap);
       };
     }
     a.neumann = neumann;

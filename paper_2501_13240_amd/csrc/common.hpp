@@ -12,8 +12,8 @@
 namespace sem {
 
 constexpr int kMaxOrder = 10;           // the solver family uses p <= 10 (Sec. 4.1)
-constexpr int kVecBlock = 256;          // threads per block of the vector kernels
-constexpr int kReduceBlocks = 1024;     // fixed grid of reducing kernels (deterministic sums)
+constexpr int kVecBlock = 512;          // threads per block of the vector kernels
+constexpr int kReduceBlocks = 512;      // fixed grid of reducing kernels (deterministic sums)
 constexpr int kMaxReduce = 4;           // values reduced per pass
 
 // ---------------------------------------------------------------- errors
@@ -84,7 +84,7 @@ struct CgScalars {
   int32_t neumann;  // 1 = project out the constant mode
   int32_t flexible; // 1 = Polak-Ribiere beta
   int32_t pad2;
-  uint32_t cnt[4];  // block-completion counters of the reducing kernels (0 between launches)
+  double rho2[2];   // r.z of iteration k in slot k & 1
 };
 
 // Sum of the local copies perm[a..b) of one global node, in ascending order

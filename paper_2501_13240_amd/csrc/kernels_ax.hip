@@ -70,28 +70,31 @@ __global__ __launch_bounds__(Shape<N>::BT) void ax_kernel(
   const bool use_k = kf != nullptr;
   const bool use_h2 = h2 != T(0);
 
+  // Idle threads (tail of the last workgroup, padding lanes) load from a
+  // clamped valid address and discard the values, so every load below is
+  // unconditional and issued back to back.
+  const int64_t ec = ok_e ? e : E - 1;
+  for (int a = t; a < n1 * n1; a += S::BT) sD[a] = D[a];
   T uq[PPT], gq[PPT][6], kq[PPT];
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
-    const int q = tl + s * TPE;
-    const bool ok = ok_e && q < P;
-    const int64_t idx = e * P + q;
-    T v = T(0);
-    if (ok) {
-      if constexpr (GATHER) {
-        const int32_t lm = ld_stream(lmap + idx);
-        v = lm >= 0 ? u[lm] : T(0);
-      } else {
-        v = ld_stream(u + idx);
-      }
+    const int qr = tl + s * TPE;
+    const int q = qr < P ? qr : P - 1;
+    const int64_t idx = ec * P + q;
+    T v;
+    if constexpr (GATHER) {
+      const int32_t lm = ld_stream(lmap + idx);
+      v = u[lm >= 0 ? lm : 0];
+      v = lm >= 0 ? v : T(0);
+    } else {
+      v = ld_stream(u + idx);
     }
-    uq[s] = v;
-    const T* g = G + e * 6 * P + q;
+    uq[s] = ok_e ? v : T(0);
+    const T* g = G + ec * 6 * P + q;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) gq[s][c] = ok ? ld_stream(g + c * P) : T(0);
-    kq[s] = (ok && use_k) ? ld_stream(kf + idx) : T(1);
+    for (int c = 0; c < 6; ++c) gq[s][c] = ld_stream(g + c * P);
+    kq[s] = use_k ? ld_stream(kf + idx) : T(1);
   }
-  for (int a = t; a < n1 * n1; a += S::BT) sD[a] = D[a];
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
     const int q = tl + s * TPE;
@@ -172,17 +175,19 @@ __global__ __launch_bounds__(Shape<N>::BT) void kbar_kernel(
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool ok_e = slot < EPB && e < E;
   const int ss = slot < EPB ? slot : 0;
+  const int64_t ec = ok_e ? e : E - 1;
   double gq[PPT][6];
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
-    const int q = tl + s * TPE;
-    const bool ok = ok_e && q < P;
-    const double* g = G + e * 6 * P + q;
+    const int qr = tl + s * TPE;
+    const int q = qr < P ? qr : P - 1;
+    const double* g = G + ec * 6 * P + q;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) gq[s][c] = ok ? ld_stream(g + c * P) : 0.0;
-    if (slot < EPB && q < P) {
-      su[ss][q] = ok ? ld_stream(u + e * P + q) : 0.0;
-      sw[ss][q] = ok ? ld_stream(wb + e * P + q) : 0.0;
+    for (int c = 0; c < 6; ++c) gq[s][c] = ld_stream(g + c * P);
+    const double uv = ld_stream(u + ec * P + q), wv = ld_stream(wb + ec * P + q);
+    if (slot < EPB && qr < P) {
+      su[ss][q] = ok_e ? uv : 0.0;
+      sw[ss][q] = ok_e ? wv : 0.0;
     }
   }
   for (int a = t; a < n1 * n1; a += S::BT) sD[a] = D[a];

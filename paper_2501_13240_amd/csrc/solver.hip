@@ -87,36 +87,22 @@ __device__ __forceinline__ bool finite(double x) { return x == x && fabs(x) <= 1
 
 // ------------------------------------------------------------- CG kernels
 //
-// Each reducing kernel writes per-block partial sums; the block that finishes
-// last (counted with one atomic) sums all partials in block order -- a fixed
-// order, so results do not depend on scheduling -- and updates the scalars.
-// This replaces a separate single-block finalisation launch.
+// No finalisation launches and no grid-wide fences: a reducing kernel writes
+// per-block partial sums, and every block of the kernel that consumes them
+// sums all partials itself in the same fixed order, so all blocks obtain
+// bit-identical scalars (alpha, beta, the convergence decision).  Block 0
+// records them in CgScalars for the host and for later kernels.  rho is kept
+// in two slots indexed by the iteration's parity so that block 0 can store
+// the next value while other blocks still read the current one.
 
-template <int NV>
-__device__ __forceinline__ bool last_block_total(double (&v)[NV], double* __restrict__ part,
-                                                 unsigned* __restrict__ counter, double (&S)[NV]) {
-  __shared__ bool am_last;
-  block_partials<NV>(v, part);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) am_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
-  block_total<NV>(part, gridDim.x, S);
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
-  return true;
-}
-
-// w = R Q^T w_L (segmented sum); p.w, sum(w), sum(p) -> alpha
+// w = R Q^T w_L (segmented sum); partials of p.w, sum(w), sum(p)
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_gsum_alpha(int64_t nf,
-                                                          const int32_t* __restrict__ seg,
-                                                          const int32_t* __restrict__ perm,
-                                                          const T* __restrict__ wL,
-                                                          const T* __restrict__ p, T* __restrict__ w,
-                                                          double* __restrict__ part,
-                                                          CgScalars* __restrict__ sc) {
+__global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t* __restrict__ seg,
+                                                       const int32_t* __restrict__ perm,
+                                                       const T* __restrict__ wL,
+                                                       const T* __restrict__ p, T* __restrict__ w,
+                                                       double* __restrict__ part,
+                                                       const CgScalars* __restrict__ sc) {
   if (sc->done) return;
   double v[3] = {0.0, 0.0, 0.0};
   GRID_STRIDE(g, nf) {
@@ -127,107 +113,132 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_alpha(int64_t nf,
     v[1] += (double)s;
     v[2] += pg;
   }
-  double S[3];
-  if (!last_block_total<3>(v, part, &sc->cnt[0], S)) return;
-  if (threadIdx.x == 0) {
-    double pw = S[0], mw = 0.0;
-    if (sc->neumann) {
-      mw = S[1] * sc->inv_n;
-      pw -= mw * S[2];
-    }
-    sc->mean_w = mw;
-    if (!(pw > 0.0) || !finite(pw)) {
-      sc->status = 2;
-      sc->done = 1;
-      sc->alpha = 0.0;
-    } else {
-      sc->alpha = sc->rho / pw;
-    }
-  }
+  block_partials<3>(v, part);
 }
 
-// x += alpha p;  r -= alpha (w - mean_w);  r.r (and r.S r) -> convergence test
-// (and, for Jacobi, beta = r.S r / rho)
+// alpha from the p.w partials; x += alpha p;  r -= alpha (w - mean_w);
+// partials of r.r (and r.S r)
 template <typename T, bool JAC>
-__global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict__ x,
+__global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, int kit, T* __restrict__ x,
                                                       const T* __restrict__ p, T* __restrict__ r,
                                                       const T* __restrict__ w,
                                                       const T* __restrict__ dinv,
+                                                      const double* __restrict__ part_in, int nblk,
                                                       double* __restrict__ part,
                                                       CgScalars* __restrict__ sc,
-                                                      double* __restrict__ hist,
-                                                      double* __restrict__ ahist,
-                                                      double* __restrict__ bhist) {
+                                                      double* __restrict__ ahist) {
   if (sc->done) return;
-  const T a = (T)sc->alpha, mw = (T)sc->mean_w;
+  double S[3];
+  block_total<3>(part_in, nblk, S);
+  double pw = S[0], mw = 0.0;
+  if (sc->neumann) {
+    mw = S[1] * sc->inv_n;
+    pw -= mw * S[2];
+  }
+  if (!(pw > 0.0) || !finite(pw)) {  // same decision in every block
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->status = 2;
+      sc->done = 1;
+    }
+    return;
+  }
+  const double alpha = sc->rho2[kit & 1] / pw;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->alpha = alpha;
+    sc->mean_w = mw;
+    if (ahist) ahist[kit] = alpha;
+  }
+  const T a = (T)alpha, mwt = (T)mw;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(g, nf) {
     x[g] = x[g] + a * p[g];
-    const T rg = r[g] - a * (w[g] - mw);
+    const T rg = r[g] - a * (w[g] - mwt);
     r[g] = rg;
     const double rd = (double)rg;
     v[0] += rd * rd;
     if (JAC) v[1] += rd * rd * (double)dinv[g];
   }
-  double S[2];
-  if (!last_block_total<2>(v, part, &sc->cnt[1], S)) return;
-  if (threadIdx.x == 0) {
-    const double rr = S[0];
-    const int it = sc->it + 1;
+  block_partials<2>(v, part);
+}
+
+// convergence decision from the r.r partial (identical in every block);
+// block 0 records it.  Returns true if the solve continues.
+__device__ __forceinline__ bool cg_check(double rr, int kit, CgScalars* __restrict__ sc,
+                                         double* __restrict__ hist) {
+  const int it = kit + 1;
+  int status = 0;
+  bool stop = false;
+  if (!finite(rr)) {
+    status = 3;
+    stop = true;
+  } else if (!sc->fixed && rr <= sc->tol2) {
+    status = 1;
+    stop = true;
+  } else if (it >= sc->max_it) {
+    stop = true;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->it = it;
     sc->rr = rr;
     if (hist) hist[it] = sqrt(rr);
-    if (ahist) ahist[it - 1] = sc->alpha;
-    if (!finite(rr)) {
-      sc->status = 3;
-      sc->done = 1;
-    } else if (!sc->fixed && rr <= sc->tol2) {
-      sc->status = 1;
-      sc->done = 1;
-    } else if (it >= sc->max_it) {
+    if (stop) {
+      sc->status = status;
       sc->done = 1;
     }
-    if (JAC) {
-      const double rz = S[1];
-      const double beta = rz / sc->rho;
-      sc->beta = beta;
-      sc->rho = rz;
-      if (bhist) bhist[it - 1] = beta;
-    }
   }
+  return !stop;
 }
 
-// flexible (Polak-Ribiere) beta from z.r and z.(w - mean_w) of the preconditioner pass:
-// beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha z.(w - mean_w) / rho_k
-__device__ __forceinline__ void beta_flex(const double (&S)[2], CgScalars* __restrict__ sc,
-                                          double* __restrict__ bhist) {
-  const double rz = S[0], zw = S[1];
-  const double beta = -sc->alpha * zw / sc->rho;
-  sc->beta = beta;
-  sc->rho = rz;
-  if (bhist) bhist[sc->it - 1] = beta;
-  if (!finite(rz) || !finite(beta)) {
-    sc->status = 3;
-    sc->done = 1;
-  }
-}
-
+// Jacobi: check, beta = r.S r / rho, p = S r + beta p
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __restrict__ p,
+__global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, int kit, T* __restrict__ p,
                                                            const T* __restrict__ r,
                                                            const T* __restrict__ dinv,
-                                                           const CgScalars* __restrict__ sc) {
+                                                           const double* __restrict__ part_in,
+                                                           int nblk, CgScalars* __restrict__ sc,
+                                                           double* __restrict__ hist,
+                                                           double* __restrict__ bhist) {
   if (sc->done) return;
-  const T b = (T)sc->beta;
+  double S[2];
+  block_total<2>(part_in, nblk, S);
+  if (!cg_check(S[0], kit, sc, hist)) return;
+  const double rz = S[1];
+  const double beta = rz / sc->rho2[kit & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rho2[(kit + 1) & 1] = rz;
+    sc->beta = beta;
+    if (bhist) bhist[kit] = beta;
+  }
+  const T b = (T)beta;
   GRID_STRIDE(g, nf) p[g] = dinv[g] * r[g] + b * p[g];
 }
 
+// flexible CG: beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha z.(w - mean_w) / rho_k
+// from the preconditioner pass's partials (z.r, z.(w - mean_w)); p = z + beta p
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_pupdate_z(int64_t nf, T* __restrict__ p,
-                                                         const T* __restrict__ z,
-                                                         const CgScalars* __restrict__ sc) {
+__global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, int kit, T* __restrict__ p,
+                                                            const T* __restrict__ z,
+                                                            const double* __restrict__ part_in,
+                                                            int nblk, CgScalars* __restrict__ sc,
+                                                            double* __restrict__ bhist) {
   if (sc->done) return;
-  const T b = (T)sc->beta;
+  double S[2];
+  block_total<2>(part_in, nblk, S);
+  const double rz = S[0], zw = S[1];
+  const double beta = -sc->alpha * zw / sc->rho2[kit & 1];
+  if (!finite(rz) || !finite(beta)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->status = 3;
+      sc->done = 1;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rho2[(kit + 1) & 1] = rz;
+    sc->beta = beta;
+    if (bhist) bhist[kit] = beta;
+  }
+  const T b = (T)beta;
   GRID_STRIDE(g, nf) p[g] = z[g] + b * p[g];
 }
 
@@ -315,21 +326,29 @@ __global__ void k_ir_update(int64_t n, double* __restrict__ x, const float* __re
 
 // --------------------------------------------------------- Chebyshev kernels
 //
-// With FLEX the pass also reduces z.r and z.(w - mean_w) of the enclosing
-// flexible CG and its last block sets beta.
+// Inside a flexible CG (FLEX) the first pass also takes the convergence
+// decision from the r.r partials of the update, and the last pass reduces
+// z.r and z.(w - mean_w) for beta.
+
+template <bool FLEX>
+__device__ __forceinline__ bool cheb_gate(const double* __restrict__ check_in, int nblk, int kit,
+                                          CgScalars* __restrict__ sc, double* __restrict__ hist) {
+  if (!FLEX) return true;
+  double S[2];  // the update kernel writes two partials per block (r.r and an unused slot)
+  block_total<2>(check_in, nblk, S);
+  return cg_check(S[0], kit, sc, hist);
+}
 
 // d = c0 S r; r_k = r; z = d
-template <typename Tr, typename Tp, bool FLEX>
-__global__ __launch_bounds__(kVecBlock) void k_cheb_init(int64_t nf, const Tr* __restrict__ r,
-                                                         const Tp* __restrict__ dinv,
-                                                         Tp* __restrict__ d, Tp* __restrict__ rk,
-                                                         Tr* __restrict__ z, double c0,
-                                                         const Tr* __restrict__ wcg,
-                                                         double* __restrict__ part,
-                                                         CgScalars* __restrict__ sc,
-                                                         double* __restrict__ bhist) {
+template <typename Tr, typename Tp, bool FLEX, bool DOTS>
+__global__ __launch_bounds__(kVecBlock) void k_cheb_init(
+    int64_t nf, const Tr* __restrict__ r, const Tp* __restrict__ dinv, Tp* __restrict__ d,
+    Tp* __restrict__ rk, Tr* __restrict__ z, double c0, const Tr* __restrict__ wcg,
+    const double* __restrict__ check_in, int nblk, int kit, double* __restrict__ part,
+    CgScalars* __restrict__ sc, double* __restrict__ hist) {
   if (sc && sc->done) return;
-  const double mw = FLEX ? sc->mean_w : 0.0;
+  if (!cheb_gate<FLEX>(check_in, nblk, kit, sc, hist)) return;
+  const double mw = DOTS ? sc->mean_w : 0.0;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(g, nf) {
     const Tp rg = (Tp)r[g];
@@ -337,28 +356,24 @@ __global__ __launch_bounds__(kVecBlock) void k_cheb_init(int64_t nf, const Tr* _
     d[g] = dg;
     rk[g] = rg;
     z[g] = (Tr)dg;
-    if (FLEX) {
+    if (DOTS) {
       v[0] += (double)dg * (double)r[g];
       v[1] += (double)dg * ((double)wcg[g] - mw);
     }
   }
-  if constexpr (FLEX) {
-    double S[2];
-    if (!last_block_total<2>(v, part, &sc->cnt[2], S)) return;
-    if (threadIdx.x == 0) beta_flex(S, sc, bhist);
-  }
+  if constexpr (DOTS) block_partials<2>(v, part);
 }
 
 // r_k -= R Q^T w_L;  d = a d + b S r_k;  z += d
-template <typename Tp, typename Tr, bool FLEX>
+template <typename Tp, typename Tr, bool DOTS>
 __global__ __launch_bounds__(kVecBlock) void k_cheb_step(
     int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
     const Tp* __restrict__ wL, Tp* __restrict__ rk, Tp* __restrict__ d,
     const Tp* __restrict__ dinv, Tr* __restrict__ z, double ca, double cb,
     const Tr* __restrict__ rcg, const Tr* __restrict__ wcg, double* __restrict__ part,
-    CgScalars* __restrict__ sc, double* __restrict__ bhist) {
+    const CgScalars* __restrict__ sc) {
   if (sc && sc->done) return;
-  const double mw = FLEX ? sc->mean_w : 0.0;
+  const double mw = DOTS ? sc->mean_w : 0.0;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(g, nf) {
     const Tp s = segment_sum<Tp>(perm, wL, seg[g], seg[g + 1]);
@@ -368,16 +383,12 @@ __global__ __launch_bounds__(kVecBlock) void k_cheb_step(
     d[g] = dg;
     const Tr zg = z[g] + (Tr)dg;
     z[g] = zg;
-    if (FLEX) {
+    if (DOTS) {
       v[0] += (double)zg * (double)rcg[g];
       v[1] += (double)zg * ((double)wcg[g] - mw);
     }
   }
-  if constexpr (FLEX) {
-    double S[2];
-    if (!last_block_total<2>(v, part, &sc->cnt[2], S)) return;
-    if (threadIdx.x == 0) beta_flex(S, sc, bhist);
-  }
+  if constexpr (DOTS) block_partials<2>(v, part);
 }
 
 inline unsigned vgrid(int64_t n) {
@@ -400,7 +411,7 @@ sem_status SolveWork::init(const sem_mesh* m, int max_iter) {
   if (!h_sc) SEM_HIP(hipHostMalloc((void**)&h_sc, 4 * sizeof(CgScalars)));
   if (!h_red) SEM_HIP(hipHostMalloc((void**)&h_red, 64 * sizeof(double)));
   sem_status st;
-  if ((st = part.ensure(kReduceBlocks * kMaxReduce * sizeof(double)))) return st;
+  if ((st = part.ensure(3 * kReduceBlocks * kMaxReduce * sizeof(double)))) return st;
   if ((st = sc.ensure(sizeof(CgScalars)))) return st;
   if ((st = red.ensure(64 * sizeof(double)))) return st;
   const size_t hb = (size_t)(max_iter + 2) * sizeof(double);
@@ -479,25 +490,31 @@ template sem_status apply_op<float>(const sem_mesh*, SolveWork&, const Op<float>
 
 template <typename Tr, typename Tp>
 sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
-                          const Tr* r, Tr* z, int order, double lmax, CgScalars* sc,
-                          const Tr* wcg, double* part, hipStream_t s, int* applies) {
+                          const Tr* r, Tr* z, int order, double lmax, const ChebCg& cg,
+                          hipStream_t s, int* applies) {
   const int64_t nf = m->n_free;
   const unsigned nb = vgrid(nf);
   Tp* d = W.vec<Tp>(sizeof(Tp) == 8 ? W.cd : W.cd32, nf);
   Tp* rk = W.vec<Tp>(sizeof(Tp) == 8 ? W.crk : W.crk32, nf);
   Tp* wL = W.vec<Tp>(sizeof(Tp) == 8 ? W.wL : W.wL32, m->nL);
   if (!d || !rk || !wL) return fail(SEM_ENOMEM, "Chebyshev work space");
-  const bool flex = (sc != nullptr && wcg != nullptr);
-  double* bhist = W.bhist.as<double>();
+  const bool flex = cg.sc != nullptr;
+  const Tr* wcg = static_cast<const Tr*>(cg.w);
   const double c0 = 4.0 / (3.0 * lmax);
   Op<Tp> opk = op;
-  if (sc) opk.skip = &sc->done;
+  if (flex) opk.skip = &cg.sc->done;
   if (flex && order == 1)
-    hipLaunchKernelGGL((k_cheb_init<Tr, Tp, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, r, dinv, d,
-                       rk, z, c0, wcg, part, sc, bhist);
+    hipLaunchKernelGGL((k_cheb_init<Tr, Tp, true, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, r,
+                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.kit, cg.part_out, cg.sc,
+                       cg.hist);
+  else if (flex)
+    hipLaunchKernelGGL((k_cheb_init<Tr, Tp, true, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, r,
+                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.kit, cg.part_out, cg.sc,
+                       cg.hist);
   else
-    hipLaunchKernelGGL((k_cheb_init<Tr, Tp, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, r, dinv,
-                       d, rk, z, c0, wcg, part, sc, bhist);
+    hipLaunchKernelGGL((k_cheb_init<Tr, Tp, false, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, r,
+                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.kit, cg.part_out,
+                       (CgScalars*)nullptr, cg.hist);
   SEM_CHECK_LAUNCH("Chebyshev init");
   for (int k = 1; k < order; ++k) {
     sem_status st = apply_op<Tp>(m, W, opk, d, wL, s, false);
@@ -508,27 +525,24 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
     if (flex && k == order - 1)
       hipLaunchKernelGGL((k_cheb_step<Tp, Tr, true>), dim3(nb), dim3(kVecBlock), 0, s, nf,
                          m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
-                         r, wcg, part, sc, bhist);
+                         r, wcg, cg.part_out, cg.sc);
     else
       hipLaunchKernelGGL((k_cheb_step<Tp, Tr, false>), dim3(nb), dim3(kVecBlock), 0, s, nf,
                          m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
-                         r, wcg, part, sc, bhist);
+                         r, wcg, cg.part_out, cg.sc);
     SEM_CHECK_LAUNCH("Chebyshev step");
   }
   return SEM_OK;
 }
 template sem_status cheb_apply_dev<double, double>(const sem_mesh*, SolveWork&, const Op<double>&,
                                                    const double*, const double*, double*, int,
-                                                   double, CgScalars*, const double*, double*,
-                                                   hipStream_t, int*);
+                                                   double, const ChebCg&, hipStream_t, int*);
 template sem_status cheb_apply_dev<double, float>(const sem_mesh*, SolveWork&, const Op<float>&,
                                                   const float*, const double*, double*, int, double,
-                                                  CgScalars*, const double*, double*, hipStream_t,
-                                                  int*);
+                                                  const ChebCg&, hipStream_t, int*);
 template sem_status cheb_apply_dev<float, float>(const sem_mesh*, SolveWork&, const Op<float>&,
                                                  const float*, const float*, float*, int, double,
-                                                 CgScalars*, const float*, double*, hipStream_t,
-                                                 int*);
+                                                 const ChebCg&, hipStream_t, int*);
 
 // ------------------------------------------------------------------- CG
 
@@ -586,7 +600,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
     hipLaunchKernelGGL((k_init_p<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv,
                        (const T*)nullptr, part);
   } else {
-    if ((st = a.cheb(m, W, r, z, nullptr, nullptr, part, s, &res.applies))) return st;
+    if ((st = a.cheb(m, W, r, z, ChebCg(), s, &res.applies))) return st;
     hipLaunchKernelGGL((k_init_p<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv, z, part);
   }
   hipLaunchKernelGGL((k_totals<1>), dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, W.red.as<double>());
@@ -601,6 +615,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
 
   CgScalars h{};
   h.rho = rho0;
+  h.rho2[0] = rho0;
   h.bb = bb;
   h.tol2 = tol2;
   h.rr = rr0;
@@ -621,20 +636,33 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
 
   Op<T> op_it = a.op;
   op_it.skip = &sc->done;
-  auto iteration = [&]() -> sem_status {
+  double* partA = part;
+  double* partB = part + kReduceBlocks * kMaxReduce;
+  double* partC = part + 2 * kReduceBlocks * kMaxReduce;
+  auto iteration = [&](int kit) -> sem_status {
     sem_status e;
     if ((e = apply_op<T>(m, W, op_it, p, wL, s, a.profile))) return e;
-    hipLaunchKernelGGL((k_gsum_alpha<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
-                       m->fperm.as<int32_t>(), wL, p, w, part, sc);
+    hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
+                       m->fperm.as<int32_t>(), wL, p, w, partA, sc);
     if (jac) {
-      hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w,
-                         a.dinv, part, sc, hist, ahist, bhist);
-      hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv, sc);
+      hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, kit, x, p, r, w,
+                         a.dinv, partA, (int)nb, partB, sc, ahist);
+      hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, kit, p, r, a.dinv,
+                         partB, (int)nb, sc, hist, bhist);
     } else {
-      hipLaunchKernelGGL((k_update<T, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w,
-                         a.dinv, part, sc, hist, ahist, bhist);
-      if ((e = a.cheb(m, W, r, z, sc, w, part, s, nullptr))) return e;
-      hipLaunchKernelGGL((k_pupdate_z<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, z, sc);
+      hipLaunchKernelGGL((k_update<T, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, kit, x, p, r, w,
+                         a.dinv, partA, (int)nb, partB, sc, ahist);
+      ChebCg cg;
+      cg.sc = sc;
+      cg.w = w;
+      cg.check_in = partB;
+      cg.nblk = (int)nb;
+      cg.kit = kit;
+      cg.part_out = partC;
+      cg.hist = hist;
+      if ((e = a.cheb(m, W, r, z, cg, s, nullptr))) return e;
+      hipLaunchKernelGGL((k_pupdate_flex<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, kit, p, z, partC,
+                         (int)nb, sc, bhist);
     }
     SEM_CHECK_LAUNCH("CG iteration");
     return SEM_OK;
@@ -643,7 +671,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   int enq = 0;
   if (a.fixed) {
     for (; enq < a.max_it; ++enq)
-      if ((st = iteration())) return st;
+      if ((st = iteration(enq))) return st;
     SEM_HIP(hipMemcpyAsync(&W.h_sc[0], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
     h = W.h_sc[0];
@@ -660,7 +688,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
     while (!finished) {
       const int n_now = std::min(chunk, a.max_it - enq);
       for (int c = 0; c < n_now; ++c)
-        if ((st = iteration())) break;
+        if ((st = iteration(enq + c))) break;
       enq += n_now;
       if (st) break;
       SEM_HIP(hipMemcpyAsync(&W.h_sc[slot], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));

@@ -43,10 +43,23 @@ struct CgResult {
   double bnorm = 0.0, rnorm = 0.0;
 };
 
+// Coupling of a Chebyshev pass to an enclosing flexible CG iteration (all
+// null/zero for a stand-alone apply): the first pass takes the convergence
+// decision from the update's r.r partials `check_in`, the last one writes the
+// z.r and z.(w - mean_w) partials for beta into `part_out`.
+struct ChebCg {
+  CgScalars* sc = nullptr;
+  const void* w = nullptr;          // w = A p of the CG iteration (CG vector type)
+  const double* check_in = nullptr;
+  int nblk = 0;
+  int kit = 0;
+  double* part_out = nullptr;
+  double* hist = nullptr;
+};
+
 template <typename T>
 using ChebFn = std::function<sem_status(const sem_mesh*, SolveWork&, const T* r, T* z,
-                                        CgScalars* sc, const T* wcg, double* part,
-                                        hipStream_t s, int* applies)>;
+                                        const ChebCg& cg, hipStream_t s, int* applies)>;
 
 template <typename T, typename Tp>
 struct CgArgs {
@@ -75,8 +88,8 @@ sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* x
 
 template <typename Tr, typename Tp>
 sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
-                          const Tr* r, Tr* z, int order, double lmax, CgScalars* sc,
-                          const Tr* wcg, double* part, hipStream_t s, int* applies);
+                          const Tr* r, Tr* z, int order, double lmax, const ChebCg& cg,
+                          hipStream_t s, int* applies);
 
 template <typename T, typename Tp>
 sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgResult& res,

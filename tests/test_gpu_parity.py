@@ -205,8 +205,9 @@ def test_pcg_neumann_matches_oracle():
 
 
 @pytest.mark.parametrize("precond_prec", ["fp64", "fp32"])
-def test_pcg_chebyshev_reaches_tolerance(precond_prec):
-    m, fld = config_mesh(1)
+@pytest.mark.parametrize("N", [7, 9])
+def test_pcg_chebyshev_reaches_tolerance(precond_prec, N):
+    m, fld = config_mesh(1, N=N)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
     P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
     f = fld["f"] * 3 * np.pi ** 2
@@ -216,7 +217,9 @@ def test_pcg_chebyshev_reaches_tolerance(precond_prec):
     res, xf = _true_rel_residual(P, x.cpu().numpy(), b_or)
     ref = P.solve(b_or, rtol=1e-10, precond="chebyshev", rho_hat=st["lmax"])
     print(f"chebyshev {precond_prec}: iters gpu {st['iters']} oracle {ref['iters']} res {res:.2e}")
-    assert res <= 1.2e-10
+    # the recurrence residual the solver stops on must be the true residual
+    assert abs(st["rel_res"] - res) <= 0.05 * res
+    assert res <= 1.0e-10
     assert abs(st["iters"] - ref["iters"]) <= 3
     assert rel(xf, ref["x"]) <= 1e-8
 
