@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=8)
+    ap.add_argument("--cpu-sample-iters", type=int, default=150)
     ap.add_argument("--ax-reps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for counter calibration)")
@@ -69,6 +69,27 @@ def cpu_baseline(iters):
                         f"32x8x16-element slice of the same recipe ({P.num.n} unique nodes), "
                         f"single-threaded einsum/bincount, {dt:.1f} s"),
                 seconds=dt)
+
+
+def counter_traffic():
+    """HBM bytes per operator launch from the committed rocprofv3 counter summary,
+    or None when the operator source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "ax_N7_convection_box_traffic.txt")
+    src = os.path.join(ROOT, "paper_2501_13240_amd", "csrc", "kernels_ax.hip")
+    try:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", " ")):
+                key, val = line.split(":", 1)
+                kv[key.strip()] = val.strip()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("kernels_ax.hip sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def true_rel_residual(sem, M, b, x, k=None, h2=0.0):
@@ -220,7 +241,8 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": counter_traffic(),
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "ax_kernel<7,double,gather> (element operator, 64 B/local point)",
             "avg_launch_us": ax_avg_ms * 1e3,
             "launches_timed": ax_n,
