@@ -103,7 +103,8 @@ typedef struct {
   double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2 over the free unique nodes */
   int32_t max_iter;     /* CG iteration limit (mode CG) or total inner-iteration limit (MIXED_IR) */
   int32_t fixed_iters;  /* mode CG only: 1 = run exactly max_iter iterations (no early exit) */
-  double inner_rtol;    /* MIXED_IR: relative residual reduction of each inner solve (default 1e-5) */
+  double inner_rtol;    /* MIXED_IR: relative residual reduction of each inner solve (default 1e-5);
+                           the last steps only reduce by what is still missing to reach rtol */
   int32_t max_outer;    /* MIXED_IR: refinement step limit (default 30) */
   int32_t check_every;  /* iterations between convergence read-backs (0 = automatic) */
   int32_t profile;      /* 1: time every FP64 operator-apply kernel with HIP events into stats */

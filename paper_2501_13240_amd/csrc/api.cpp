@@ -629,6 +629,9 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
       const double shift = neumann ? rr_sum[1] / (double)nf : 0.0;
       if ((st = ir_prepare(m, r, b32, shift, 1.0 / rnorm, s))) return st;
       a.max_it = std::max(1, opts.max_iter - iters);
+      // inner reduction: inner_rtol, or only what is still missing to reach rtol
+      // (with a 0.3 safety factor), so the last refinement step is short
+      a.rtol = std::min(0.5, std::max(opts.inner_rtol, 0.3 * opts.rtol / rel));
       CgResult res;
       if ((st = cg_solve<float, float>(m, W, a, res, s))) return st;
       iters += res.iters;

@@ -15,6 +15,7 @@ constexpr int kMaxOrder = 10;           // the solver family uses p <= 10 (Sec. 
 constexpr int kVecBlock = 512;          // threads per block of the vector kernels
 constexpr int kReduceBlocks = 512;      // fixed grid of reducing kernels (deterministic sums)
 constexpr int kMaxReduce = 4;           // values reduced per pass
+constexpr int64_t kGraphMaxFree = 262144;  // solves up to this size replay captured iteration graphs
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
@@ -83,9 +84,39 @@ struct CgScalars {
   int32_t fixed;    // 1 = never stop before max_it
   int32_t neumann;  // 1 = project out the constant mode
   int32_t flexible; // 1 = Polak-Ribiere beta
-  int32_t pad2;
+  int32_t kcur;     // index of the iteration in progress (set by the update kernel)
   double rho2[2];   // r.z of iteration k in slot k & 1
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8), each with its own L2.  xcd_block() renumbers them so that every
+// XCD works on one contiguous range of the index space: neighbouring elements
+// and nodes, which share data, then share an L2.  Off by default: measured on
+// the benchmark meshes it gained nothing (the memory-side Infinity Cache
+// already serves the cross-XCD re-reads); enable with -DSEM_XCD_REMAP=1.
+#ifndef SEM_XCD_REMAP
+#define SEM_XCD_REMAP 0
+#endif
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+#if SEM_XCD_REMAP
+  const int64_t x = b % kNumXcd, i = b / kNumXcd;
+  const int64_t per = nb / kNumXcd, rem = nb % kNumXcd;
+  return x * per + (x < rem ? x : rem) + i;
+#else
+  (void)nb;
+  return b;
+#endif
+}
+
+// Loop over this workgroup's contiguous chunk of [0, n) (chunks follow the
+// XCD-aware block order).
+#define BLOCK_CHUNK(idx, n)                                                          \
+  const int64_t lb_ = xcd_block(blockIdx.x, gridDim.x);                              \
+  const int64_t chunk_ = ((int64_t)(n) + gridDim.x - 1) / gridDim.x;                  \
+  const int64_t lo_ = lb_ * chunk_;                                                  \
+  const int64_t hi_ = lo_ + chunk_ < (int64_t)(n) ? lo_ + chunk_ : (int64_t)(n);       \
+  for (int64_t idx = lo_ + threadIdx.x; idx < hi_; idx += blockDim.x)
 
 // Sum of the local copies perm[a..b) of one global node, in ascending order
 // (deterministic).  The index loads of up to 8 copies are issued together,

@@ -15,6 +15,13 @@
 // so the t-direction coefficients D[k][l] are wave-uniform and come from
 // scalar loads instead of LDS.
 //
+// For larger N the scalar contractions make the kernel LDS-bound (each
+// point reads 2 (N+1) values per direction per phase from LDS).  There the
+// contractions run on the matrix cores instead (ax_mfma_kernel): each
+// direction is a batch of 16-column tiles C = D X (or D^T X) with X gathered
+// from the element block in LDS, 16x16x4 MFMAs in FP64 or FP32, so every LDS
+// value feeds a whole tile column instead of one output.
+//
 // Per local point the FP64 apply streams u (8 B), six geometric factors
 // (48 B, planar layout [E][6][P]) and w (8 B): 64 B.
 #include "common.hpp"
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(Shape<N>::BT) void ax_kernel(
   const int t = threadIdx.x;
   const int slot = t / TPE;
   const int tl = t - slot * TPE;
-  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + slot;
   const bool ok_e = slot < EPB && e < E;
   const int ss = slot < EPB ? slot : 0;
   const bool use_k = kf != nullptr;
@@ -158,6 +165,189 @@ __global__ __launch_bounds__(Shape<N>::BT) void ax_kernel(
   }
 }
 
+
+// ------------------------------------------------------------ matrix cores
+
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+// 16x16x4 MFMA: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; result
+// element (i, j) in lane 16 (i % 4) + j, register i / 4 for FP64 and in lane
+// 16 (i / 4) + j, register i % 4 for FP32 (checked on the device).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef v4d_t V;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f_t V;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// One 16-column tile of a contraction along direction DIR of the element
+// block src ([k][j][i], n1 per direction): out[.., row, ..] = sum_l A[row][l]
+// src[.., l, ..], A = D (forward) or D^T (transposed), given as per-lane
+// fragments.  Columns enumerate the two other indices: DIR 0 (along i):
+// col = k n1 + j; DIR 1 (along j): col = k n1 + i; DIR 2 (along k): col =
+// j n1 + i.  ACC adds into dst instead of storing.
+template <int n1, typename T, int DIR, bool ACC>
+__device__ __forceinline__ void contract_tile(const T* __restrict__ src, T* __restrict__ dst,
+                                              const T (&afrag)[(n1 + 3) / 4], int tile, int lane) {
+  constexpr int P2 = n1 * n1, KS = (n1 + 3) / 4;
+  const int col = tile * 16 + (lane & 15);
+  const int kk = lane >> 4;
+  const bool cval = col < P2;
+  const int c1 = cval ? col / n1 : 0, c0 = cval ? col % n1 : 0;
+  typename Mfma<T>::V acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int l = 4 * s + kk;
+    T b = T(0);
+    if (cval && l < n1) {
+      const int a = DIR == 0 ? c1 * P2 + c0 * n1 + l : DIR == 1 ? c1 * P2 + l * n1 + c0 : l * P2 + col;
+      b = src[a];
+    }
+    acc = Mfma<T>::mma(afrag[s], b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = Mfma<T>::row(lane, r);
+    if (cval && row < n1) {
+      const int a =
+          DIR == 0 ? c1 * P2 + c0 * n1 + row : DIR == 1 ? c1 * P2 + row * n1 + c0 : row * P2 + col;
+      if (ACC) dst[a] += acc[r];
+      else dst[a] = acc[r];
+    }
+  }
+}
+
+template <int N>
+struct MShape {
+  static constexpr int n1 = N + 1;
+  static constexpr int P2 = n1 * n1;
+  static constexpr int P = P2 * n1;
+  static constexpr int TPB = P <= 729 ? 256 : 512;   // threads per element (= per workgroup)
+  static constexpr int PPT = (P + TPB - 1) / TPB;    // points per thread
+  static constexpr int NT = (P2 + 15) / 16;          // 16-column tiles per direction
+  static constexpr int KS = (n1 + 3) / 4;            // K steps of 4
+  static constexpr int NW = TPB / 64;                // wavefronts
+};
+
+// Operator with matrix-core contractions, one element per workgroup.
+// Phases: loads -> forward contractions (3 NT tiles over the wavefronts) ->
+// pointwise metric and k -> transposed contractions accumulated direction
+// by direction into the (now free) input block -> stores.
+template <int N, typename T, bool GATHER>
+__global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
+    const T* __restrict__ u, const int32_t* __restrict__ lmap, T* __restrict__ w,
+    const T* __restrict__ kf, const T h2, const T* __restrict__ G, const T* __restrict__ B,
+    const T* __restrict__ D, const int64_t E, const int32_t* __restrict__ skip) {
+  using S = MShape<N>;
+  constexpr int n1 = S::n1, P = S::P, TPB = S::TPB, PPT = S::PPT, NT = S::NT, KS = S::KS,
+                NW = S::NW;
+  if (skip && *skip) return;  // uniform over the grid
+  __shared__ T su[P];
+  __shared__ T sa[3][P];
+  T* so = su;  // output accumulator, reuses the input block after the forward phase
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t e = blockIdx.x;
+  const bool use_k = kf != nullptr;
+  const bool use_h2 = h2 != T(0);
+  (void)E;
+
+  T uq[PPT], gq[PPT][6], kq[PPT];
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int qr = t + s * TPB;
+    const int q = qr < P ? qr : P - 1;
+    const int64_t idx = e * P + q;
+    if constexpr (GATHER) {
+      const int32_t lm = ld_stream(lmap + idx);
+      const T v = u[lm >= 0 ? lm : 0];
+      uq[s] = lm >= 0 ? v : T(0);
+    } else {
+      uq[s] = ld_stream(u + idx);
+    }
+    const T* g = G + e * 6 * P + q;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gq[s][c] = ld_stream(g + c * P);
+    kq[s] = use_k ? ld_stream(kf + idx) : T(1);
+  }
+  T af[KS], at[KS];
+  {
+    const int row = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int l = 4 * s + kk;
+      const bool ok = row < n1 && l < n1;
+      af[s] = ok ? D[row * n1 + l] : T(0);
+      at[s] = ok ? D[l * n1 + row] : T(0);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int q = t + s * TPB;
+    if (q < P) su[q] = uq[s];
+  }
+  __syncthreads();
+  for (int job = wv; job < 3 * NT; job += NW) {
+    const int dir = job / NT, tile = job - dir * NT;
+    if (dir == 0) contract_tile<n1, T, 0, false>(su, sa[0], af, tile, lane);
+    else if (dir == 1) contract_tile<n1, T, 1, false>(su, sa[1], af, tile, lane);
+    else contract_tile<n1, T, 2, false>(su, sa[2], af, tile, lane);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int q = t + s * TPB;
+    if (q < P) {
+      const T ur = sa[0][q], us = sa[1][q], ut = sa[2][q];
+      const T* gc = gq[s];
+      T vr = gc[0] * ur + gc[1] * us + gc[2] * ut;
+      T vs = gc[1] * ur + gc[3] * us + gc[4] * ut;
+      T vt = gc[2] * ur + gc[4] * us + gc[5] * ut;
+      if (use_k) {
+        vr *= kq[s];
+        vs *= kq[s];
+        vt *= kq[s];
+      }
+      sa[0][q] = vr;
+      sa[1][q] = vs;
+      sa[2][q] = vt;
+    }
+  }
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 0, false>(sa[0], so, at, tile, lane);
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 1, true>(sa[1], so, at, tile, lane);
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 2, true>(sa[2], so, at, tile, lane);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int q = t + s * TPB;
+    if (q < P) {
+      const int64_t idx = e * P + q;
+      T acc = so[q];
+      if (use_h2) acc += h2 * ld_stream(B + idx) * uq[s];
+      st_stream(acc, w + idx);
+    }
+  }
+}
+
+// which element-operator kernel serves order N: the matrix-core one from
+// N = 5 on (measured faster there), the scalar one below
+constexpr bool use_mfma(int N) { return N >= 5; }
+
 // kbar_q = sum_ab (D_a wbar)_q G_ab,q (D_b u)_q: the derivative of the
 // operator in k contracted with a cotangent (same mapping, 72 B per point).
 template <int N>
@@ -229,6 +419,16 @@ __global__ void mass_kernel(int64_t n, const T* __restrict__ B, const T* __restr
 template <int N, typename T>
 hipError_t run_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
                   const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip) {
+  if constexpr (use_mfma(N)) {
+    using M = MShape<N>;
+    if (lmap)
+      hipLaunchKernelGGL((ax_mfma_kernel<N, T, true>), dim3((unsigned)m->E), dim3(M::TPB), 0, s, u,
+                         lmap, w, k, h2, G, B, D, m->E, skip);
+    else
+      hipLaunchKernelGGL((ax_mfma_kernel<N, T, false>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                         u, lmap, w, k, h2, G, B, D, m->E, skip);
+    return hipGetLastError();
+  }
   using S = Shape<N>;
   const int64_t grid = (m->E + S::EPB - 1) / S::EPB;
   if (lmap)

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t
                                                        const CgScalars* __restrict__ sc) {
   if (sc->done) return;
   double v[3] = {0.0, 0.0, 0.0};
-  GRID_STRIDE(g, nf) {
+  BLOCK_CHUNK(g, nf) {
     const T s = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
     w[g] = s;
     const double pg = (double)p[g];
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t
 // alpha from the p.w partials; x += alpha p;  r -= alpha (w - mean_w);
 // partials of r.r (and r.S r)
 template <typename T, bool JAC>
-__global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, int kit, T* __restrict__ x,
+__global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict__ x,
                                                       const T* __restrict__ p, T* __restrict__ r,
                                                       const T* __restrict__ w,
                                                       const T* __restrict__ dinv,
@@ -128,6 +128,9 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, int kit, T* __
                                                       CgScalars* __restrict__ sc,
                                                       double* __restrict__ ahist) {
   if (sc->done) return;
+  // the iteration index lives on the device (so a captured chunk of
+  // iterations can be replayed): it is only advanced by later kernels
+  const int kit = sc->it;
   double S[3];
   block_total<3>(part_in, nblk, S);
   double pw = S[0], mw = 0.0;
@@ -146,11 +149,12 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, int kit, T* __
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->alpha = alpha;
     sc->mean_w = mw;
+    sc->kcur = kit;
     if (ahist) ahist[kit] = alpha;
   }
   const T a = (T)alpha, mwt = (T)mw;
   double v[2] = {0.0, 0.0};
-  GRID_STRIDE(g, nf) {
+  BLOCK_CHUNK(g, nf) {
     x[g] = x[g] + a * p[g];
     const T rg = r[g] - a * (w[g] - mwt);
     r[g] = rg;
@@ -191,7 +195,7 @@ __device__ __forceinline__ bool cg_check(double rr, int kit, CgScalars* __restri
 
 // Jacobi: check, beta = r.S r / rho, p = S r + beta p
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, int kit, T* __restrict__ p,
+__global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __restrict__ p,
                                                            const T* __restrict__ r,
                                                            const T* __restrict__ dinv,
                                                            const double* __restrict__ part_in,
@@ -199,6 +203,7 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, int kit, 
                                                            double* __restrict__ hist,
                                                            double* __restrict__ bhist) {
   if (sc->done) return;
+  const int kit = sc->kcur;
   double S[2];
   block_total<2>(part_in, nblk, S);
   if (!cg_check(S[0], kit, sc, hist)) return;
@@ -210,18 +215,19 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, int kit, 
     if (bhist) bhist[kit] = beta;
   }
   const T b = (T)beta;
-  GRID_STRIDE(g, nf) p[g] = dinv[g] * r[g] + b * p[g];
+  BLOCK_CHUNK(g, nf) p[g] = dinv[g] * r[g] + b * p[g];
 }
 
 // flexible CG: beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha z.(w - mean_w) / rho_k
 // from the preconditioner pass's partials (z.r, z.(w - mean_w)); p = z + beta p
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, int kit, T* __restrict__ p,
+__global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, T* __restrict__ p,
                                                             const T* __restrict__ z,
                                                             const double* __restrict__ part_in,
                                                             int nblk, CgScalars* __restrict__ sc,
                                                             double* __restrict__ bhist) {
   if (sc->done) return;
+  const int kit = sc->kcur;
   double S[2];
   block_total<2>(part_in, nblk, S);
   const double rz = S[0], zw = S[1];
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, int kit,
     if (bhist) bhist[kit] = beta;
   }
   const T b = (T)beta;
-  GRID_STRIDE(g, nf) p[g] = z[g] + b * p[g];
+  BLOCK_CHUNK(g, nf) p[g] = z[g] + b * p[g];
 }
 
 // ----------------------------------------------------- init / misc kernels
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(kVecBlock) void k_residual(int64_t nf, const int32_
                                                         const T* __restrict__ b, T* __restrict__ r,
                                                         double* __restrict__ part) {
   double v[2] = {0.0, 0.0};
-  GRID_STRIDE(g, nf) {
+  BLOCK_CHUNK(g, nf) {
     const T s = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
     const T rg = b[g] - s;
     r[g] = rg;
@@ -268,7 +274,7 @@ __global__ __launch_bounds__(kVecBlock) void k_dots(int64_t nf, const T* __restr
                                                     const T* __restrict__ b,
                                                     double* __restrict__ part) {
   double v[3] = {0.0, 0.0, 0.0};
-  GRID_STRIDE(g, nf) {
+  BLOCK_CHUNK(g, nf) {
     const double ag = (double)a[g];
     const double bg = b ? (double)b[g] : ag;
     v[0] += ag * bg;
@@ -294,7 +300,7 @@ __global__ __launch_bounds__(kVecBlock) void k_init_p(int64_t nf, T* __restrict_
                                                       const T* __restrict__ z,
                                                       double* __restrict__ part) {
   double v[1] = {0.0};
-  GRID_STRIDE(g, nf) {
+  BLOCK_CHUNK(g, nf) {
     const T pg = z ? z[g] : dinv[g] * r[g];
     p[g] = pg;
     v[0] += (double)pg * (double)r[g];
@@ -331,9 +337,10 @@ __global__ void k_ir_update(int64_t n, double* __restrict__ x, const float* __re
 // z.r and z.(w - mean_w) for beta.
 
 template <bool FLEX>
-__device__ __forceinline__ bool cheb_gate(const double* __restrict__ check_in, int nblk, int kit,
+__device__ __forceinline__ bool cheb_gate(const double* __restrict__ check_in, int nblk,
                                           CgScalars* __restrict__ sc, double* __restrict__ hist) {
   if (!FLEX) return true;
+  const int kit = sc->kcur;
   double S[2];  // the update kernel writes two partials per block (r.r and an unused slot)
   block_total<2>(check_in, nblk, S);
   return cg_check(S[0], kit, sc, hist);
@@ -344,13 +351,13 @@ template <typename Tr, typename Tp, bool FLEX, bool DOTS>
 __global__ __launch_bounds__(kVecBlock) void k_cheb_init(
     int64_t nf, const Tr* __restrict__ r, const Tp* __restrict__ dinv, Tp* __restrict__ d,
     Tp* __restrict__ rk, Tr* __restrict__ z, double c0, const Tr* __restrict__ wcg,
-    const double* __restrict__ check_in, int nblk, int kit, double* __restrict__ part,
+    const double* __restrict__ check_in, int nblk, double* __restrict__ part,
     CgScalars* __restrict__ sc, double* __restrict__ hist) {
   if (sc && sc->done) return;
-  if (!cheb_gate<FLEX>(check_in, nblk, kit, sc, hist)) return;
+  if (!cheb_gate<FLEX>(check_in, nblk, sc, hist)) return;
   const double mw = DOTS ? sc->mean_w : 0.0;
   double v[2] = {0.0, 0.0};
-  GRID_STRIDE(g, nf) {
+  BLOCK_CHUNK(g, nf) {
     const Tp rg = (Tp)r[g];
     const Tp dg = (Tp)c0 * dinv[g] * rg;
     d[g] = dg;
@@ -375,7 +382,7 @@ __global__ __launch_bounds__(kVecBlock) void k_cheb_step(
   if (sc && sc->done) return;
   const double mw = DOTS ? sc->mean_w : 0.0;
   double v[2] = {0.0, 0.0};
-  GRID_STRIDE(g, nf) {
+  BLOCK_CHUNK(g, nf) {
     const Tp s = segment_sum<Tp>(perm, wL, seg[g], seg[g + 1]);
     const Tp rkg = rk[g] - s;
     const Tp dg = (Tp)ca * d[g] + (Tp)cb * dinv[g] * rkg;
@@ -400,7 +407,14 @@ inline unsigned vgrid(int64_t n) {
 
 // ------------------------------------------------------------ SolveWork
 
+sem_status SolveWork::capture_stream(hipStream_t* out) {
+  if (!cap) SEM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  *out = cap;
+  return SEM_OK;
+}
+
 SolveWork::~SolveWork() {
+  if (cap) (void)hipStreamDestroy(cap);
   if (h_sc) (void)hipHostFree(h_sc);
   if (h_red) (void)hipHostFree(h_red);
   for (auto& e : ev) (void)hipEventDestroy(e);
@@ -505,15 +519,15 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
   if (flex) opk.skip = &cg.sc->done;
   if (flex && order == 1)
     hipLaunchKernelGGL((k_cheb_init<Tr, Tp, true, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, r,
-                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.kit, cg.part_out, cg.sc,
+                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.part_out, cg.sc,
                        cg.hist);
   else if (flex)
     hipLaunchKernelGGL((k_cheb_init<Tr, Tp, true, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, r,
-                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.kit, cg.part_out, cg.sc,
+                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.part_out, cg.sc,
                        cg.hist);
   else
     hipLaunchKernelGGL((k_cheb_init<Tr, Tp, false, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, r,
-                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.kit, cg.part_out,
+                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.part_out,
                        (CgScalars*)nullptr, cg.hist);
   SEM_CHECK_LAUNCH("Chebyshev init");
   for (int k = 1; k < order; ++k) {
@@ -639,46 +653,94 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   double* partA = part;
   double* partB = part + kReduceBlocks * kMaxReduce;
   double* partC = part + 2 * kReduceBlocks * kMaxReduce;
-  auto iteration = [&](int kit) -> sem_status {
+  auto iteration = [&](hipStream_t ss) -> sem_status {
     sem_status e;
-    if ((e = apply_op<T>(m, W, op_it, p, wL, s, a.profile))) return e;
-    hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
+    if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile))) return e;
+    hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, m->fseg.as<int32_t>(),
                        m->fperm.as<int32_t>(), wL, p, w, partA, sc);
     if (jac) {
-      hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, kit, x, p, r, w,
+      hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
                          a.dinv, partA, (int)nb, partB, sc, ahist);
-      hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, kit, p, r, a.dinv,
+      hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, r, a.dinv,
                          partB, (int)nb, sc, hist, bhist);
     } else {
-      hipLaunchKernelGGL((k_update<T, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, kit, x, p, r, w,
+      hipLaunchKernelGGL((k_update<T, false>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
                          a.dinv, partA, (int)nb, partB, sc, ahist);
       ChebCg cg;
       cg.sc = sc;
       cg.w = w;
       cg.check_in = partB;
       cg.nblk = (int)nb;
-      cg.kit = kit;
       cg.part_out = partC;
       cg.hist = hist;
-      if ((e = a.cheb(m, W, r, z, cg, s, nullptr))) return e;
-      hipLaunchKernelGGL((k_pupdate_flex<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, kit, p, z, partC,
+      if ((e = a.cheb(m, W, r, z, cg, ss, nullptr))) return e;
+      hipLaunchKernelGGL((k_pupdate_flex<T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, z, partC,
                          (int)nb, sc, bhist);
     }
     SEM_CHECK_LAUNCH("CG iteration");
     return SEM_OK;
   };
 
+  // Iterations between convergence read-backs; one chunk is always queued
+  // ahead of the one being polled, and kernels of a finished solve return at
+  // once, so overshooting the last iteration costs only empty launches.
+  int chunk = a.check_every;
+  if (chunk <= 0)
+    chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, 2000000 / std::max<int64_t>(nf, 1)));
+  chunk = std::max(1, std::min(chunk, std::max(a.max_it, 1)));
+  // Small problems are launch-bound: capture one chunk of iterations as a HIP
+  // graph (the iteration index lives on the device, so the same graph serves
+  // every chunk) and replay it.
+  hipGraphExec_t gexec = nullptr;
+  struct GraphGuard {
+    hipGraphExec_t* g;
+    ~GraphGuard() {
+      if (*g) (void)hipGraphExecDestroy(*g);
+    }
+  } gguard{&gexec};
+  if (!a.profile && nf <= kGraphMaxFree && a.max_it > 0) {
+    hipStream_t cs;
+    if ((st = W.capture_stream(&cs))) return st;
+    SEM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    sem_status cst = SEM_OK;
+    for (int c = 0; c < chunk && !cst; ++c) cst = iteration(cs);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (cst) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cst;
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ce != hipSuccess) {
+      gexec = nullptr;
+      return hip_fail(ce, "hipGraphInstantiate");
+    }
+  }
+  auto run_chunk = [&](int n) -> sem_status {
+    if (gexec) {
+      SEM_HIP(hipGraphLaunch(gexec, s));
+      return SEM_OK;
+    }
+    for (int c = 0; c < n; ++c) {
+      sem_status e = iteration(s);
+      if (e) return e;
+    }
+    return SEM_OK;
+  };
+
   int enq = 0;
   if (a.fixed) {
-    for (; enq < a.max_it; ++enq)
-      if ((st = iteration(enq))) return st;
+    while (enq < a.max_it) {
+      const int n_now = gexec ? chunk : a.max_it - enq;
+      if ((st = run_chunk(n_now))) return st;
+      enq += n_now;
+    }
     SEM_HIP(hipMemcpyAsync(&W.h_sc[0], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
     h = W.h_sc[0];
   } else {
-    // keep one chunk queued ahead of the one being polled
-    int chunk = a.check_every;
-    if (chunk <= 0) chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, 2000000 / std::max<int64_t>(nf, 1)));
     hipEvent_t evs[2];
     SEM_HIP(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
     SEM_HIP(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
@@ -686,11 +748,9 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
     bool have_prev = false;
     bool finished = false;
     while (!finished) {
-      const int n_now = std::min(chunk, a.max_it - enq);
-      for (int c = 0; c < n_now; ++c)
-        if ((st = iteration(enq + c))) break;
+      const int n_now = gexec ? chunk : std::min(chunk, a.max_it - enq);
+      if ((st = run_chunk(n_now))) break;
       enq += n_now;
-      if (st) break;
       SEM_HIP(hipMemcpyAsync(&W.h_sc[slot], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
       SEM_HIP(hipEventRecord(evs[slot], s));
       if (have_prev || enq >= a.max_it) {

@@ -19,7 +19,9 @@ struct SolveWork {
   double* h_red = nullptr;    // pinned reduction results
   std::vector<hipEvent_t> ev; // profiling events
   int ev_used = 0;
+  hipStream_t cap = nullptr;  // stream used only to capture iteration graphs
   ~SolveWork();
+  sem_status capture_stream(hipStream_t* out);
   sem_status init(const sem_mesh* m, int max_iter);
   template <typename T> T* vec(DevBuf& b, int64_t n);
 };
@@ -52,7 +54,6 @@ struct ChebCg {
   const void* w = nullptr;          // w = A p of the CG iteration (CG vector type)
   const double* check_in = nullptr;
   int nblk = 0;
-  int kit = 0;
   double* part_out = nullptr;
   double* hist = nullptr;
 };

@@ -280,3 +280,24 @@ def test_solve_errors_are_reported():
     # warm start: resume from the returned iterate and reach the tolerance
     x2, st2 = sem.solve(M, b, x0=x, rtol=1e-10)
     assert st2["converged"] == 1
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "chebyshev"])
+def test_graph_replayed_solve_matches_eager_launches(precond):
+    """Small solves replay a captured chunk of iterations; profiling forces
+    eager launches.  Both must give bit-identical iterates, replay after
+    replay, with eager work in between."""
+    m, fld = config_mesh(1, N=5)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    b = sem.gs(M, sem.mass(M, dev(fld["f"])))
+    x_e, st_e = sem.solve(M, b, precond=precond, rtol=1e-10, profile=True)
+    assert st_e["ax_launches"] > 0
+    for rep in range(3):
+        x_g, st_g = sem.solve(M, b, precond=precond, rtol=1e-10)
+        assert st_g["iters"] == st_e["iters"]
+        assert torch.equal(x_g, x_e), rep
+        sem.ax(M, x_g)  # eager work between replays
+        torch.cuda.synchronize()
+    xf_e, _ = sem.solve(M, b, precond=precond, max_iter=37, fixed_iters=True, profile=True)
+    xf_g, _ = sem.solve(M, b, precond=precond, max_iter=37, fixed_iters=True)
+    assert torch.equal(xf_e, xf_g)
