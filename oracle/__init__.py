@@ -29,7 +29,8 @@ states the textbook definition it follows and each is pinned by a test under
 
 from .gll import gll_nodes_weights, deriv_matrix, deriv_matrix_barycentric, legendre
 from .geometry import geometric_factors
-from .operator import local_apply, local_diagonal, mass_apply, kgrad_contraction
+from .operator import (local_apply, local_diagonal, mass_apply, kgrad_contraction,
+                       local_apply_lowprec, local_apply_majorant, round_to_format, block_scale)
 from .assembly import Numbering, explicit_matrix, element_matrices
 from .solvers import Problem, pcg, chebyshev_apply, lanczos_lmax
 from .grad import solve_and_adjoint_gradient
@@ -44,6 +45,10 @@ __all__ = [
     "local_diagonal",
     "mass_apply",
     "kgrad_contraction",
+    "local_apply_lowprec",
+    "local_apply_majorant",
+    "round_to_format",
+    "block_scale",
     "Numbering",
     "explicit_matrix",
     "element_matrices",

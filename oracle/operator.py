@@ -101,3 +101,77 @@ def kgrad_contraction(u, wbar, G, N):
     wr, ws, wt = _grads(wbar, N, D)
     vr, vs, vt = _metric_times(G, N, ur, us, ut)
     return (wr * vr + ws * vs + wt * vt).reshape(u.shape)
+
+
+# --------------------------------------------------------------------------
+# Low-precision contraction variant (the preconditioner's matrix-core form).
+#
+# The derivative contractions take 16-bit operands and accumulate exactly
+# (16-bit x 16-bit products are exact in FP32; the sum is formed here in
+# FP64); the pointwise metric, k and the mass term stay in working precision.
+# Operands rounded: D (once), the element block of u before D_a, and each
+# v_a before D_a^T.  For IEEE half precision every block is first scaled by a
+# power of two that puts its largest magnitude in [2^14, 2^15), so that values
+# far below one (a residual late in a solve, metric-weighted derivatives on
+# small elements) keep all their bits; bfloat16 has FP32's exponent range and
+# is not scaled.  Both formats round to nearest, ties to even, from FP32.
+
+def round_to_format(x, fmt):
+    """Round FP32 values of x to 'bf16' (8 significant bits, FP32 exponent
+    range) or 'fp16' (IEEE binary16), nearest-even; returned as float64."""
+    x32 = np.asarray(x, dtype=np.float32)
+    if fmt == "fp16":
+        return x32.astype(np.float16).astype(np.float64)
+    if fmt != "bf16":
+        raise ValueError(fmt)
+    bits = x32.view(np.uint32).astype(np.uint64)
+    bits = (bits + 0x7FFF + ((bits >> 16) & 1)) & 0xFFFF0000
+    return bits.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def block_scale(X, fmt):
+    """Per-element power-of-two scale of a block X (E, P): 2^(15 - e) with
+    max|X| = f 2^e, f in [0.5, 1), for 'fp16'; 1 for 'bf16' and zero blocks."""
+    E = X.shape[0]
+    if fmt != "fp16":
+        return np.ones(E)
+    m = np.max(np.abs(X.reshape(E, -1)), axis=1)
+    _, ex = np.frexp(m)
+    return np.where(m > 0, np.ldexp(1.0, 15 - ex), 1.0)
+
+
+def _round_block(X, fmt):
+    s = block_scale(X, fmt).reshape((-1,) + (1,) * (X.ndim - 1))
+    return round_to_format(X * s, fmt) / s
+
+
+def local_apply_lowprec(u, G, B, N, fmt, k=None, h2=0.0):
+    """w = A_L u with 16-bit contraction operands (format fmt); u (E, P)
+    holding FP32 values; G, B, k in working precision."""
+    D = round_to_format(deriv_matrix(N), fmt)
+    U = tensor(u, N)
+    Uq = _round_block(U, fmt)
+    ur, us, ut = d_r(D, Uq), d_s(D, Uq), d_t(D, Uq)
+    vr, vs, vt = _metric_times(G, N, ur, us, ut)
+    if k is not None:
+        K = tensor(k, N)
+        vr, vs, vt = K * vr, K * vs, K * vt
+    w = _dT_r(D, _round_block(vr, fmt)) + _dT_s(D, _round_block(vs, fmt)) \
+        + _dT_t(D, _round_block(vt, fmt))
+    w = w.reshape(u.shape)
+    if h2 != 0.0:
+        w = w + h2 * B * u
+    return w
+
+
+def local_apply_majorant(u, G, N, k=None):
+    """|D|^T (|k| sum_b |G_ab| |D_b| |u|): the operator with every entry
+    replaced by its magnitude, the scale of the rounding error bound."""
+    D = np.abs(deriv_matrix(N))
+    U = np.abs(tensor(u, N))
+    ar, as_, at = d_r(D, U), d_s(D, U), d_t(D, U)
+    vr, vs, vt = _metric_times(np.abs(G), N, ar, as_, at)
+    if k is not None:
+        K = np.abs(tensor(k, N))
+        vr, vs, vt = K * vr, K * vs, K * vt
+    return (_dT_r(D, vr) + _dT_s(D, vs) + _dT_t(D, vt)).reshape(u.shape)
