@@ -63,8 +63,14 @@ typedef enum {
  * SEM_FP64: data and arithmetic in double.
  * SEM_FP32: data and arithmetic in float (vectors passed as float).
  * SEM_BF16_MFMA / SEM_FP16_MFMA: float data; the (N+1)x(N+1) derivative
- *   contractions run on the matrix cores with bf16/fp16 operands and fp32
- *   accumulation.  Only meaningful inside the preconditioner. */
+ *   contractions run on the matrix cores with bfloat16 / IEEE-half operands
+ *   (D, the element block of u, each metric-weighted derivative block; round
+ *   to nearest even) and FP32 accumulation; metric, k and mass terms in FP32.
+ *   For half every block is first scaled by a power of two that puts its
+ *   largest magnitude in [2^14, 2^15) and the result scaled back, so small
+ *   inputs (residuals) keep their bits.  Relative error about 4e-3 (bf16) and
+ *   3e-4 (half) of the operator: meant for the preconditioner (Sec. 2.2 runs
+ *   most preconditioner work in reduced precision). */
 typedef enum { SEM_FP64 = 0, SEM_FP32 = 1, SEM_BF16_MFMA = 2, SEM_FP16_MFMA = 3 } sem_prec;
 
 typedef struct sem_mesh sem_mesh; /* opaque, library-owned */
@@ -95,8 +101,9 @@ typedef struct {
                            refinement (true residual, update and norms in FP64) around an inner
                            FP32 preconditioned CG. */
   int32_t precond;      /* sem_precond of the CG (mode CG) or of the inner CG (MIXED_IR) */
-  int32_t precond_prec; /* sem_prec of the Chebyshev preconditioner.  Mode CG: SEM_FP64 or SEM_FP32
-                           (FP64 CG with an FP32 preconditioner); MIXED_IR: SEM_FP32 */
+  int32_t precond_prec; /* sem_prec of the Chebyshev preconditioner.  Mode CG: any (FP64 CG with
+                           a lower-precision preconditioner); MIXED_IR: SEM_FP32, SEM_BF16_MFMA
+                           or SEM_FP16_MFMA (the inner CG's own operator stays FP32) */
   int32_t cheb_order;   /* Chebyshev order m >= 1 (m-1 operator applies per call); default 3 */
   double lmax;          /* Chebyshev bound rho_hat >= lambda_max(D^-1 A); <= 0: 1.1 x a
                            20-step CG-Lanczos estimate (cached per mesh for k == NULL) */
@@ -161,8 +168,8 @@ sem_status sem_get_geometry(const sem_mesh* mesh, double* G, double* B, void* st
 
 /* w = A_L(k) u, the element operator of Sec. 2.2 applied to every element
  * (unassembled).  u, w: DEVICE [E][P] of double (SEM_FP64) or float
- * (SEM_FP32); k: DEVICE [E][P] of the same type or NULL (k = 1); h2 >= 0.
- * w must not alias u. */
+ * (SEM_FP32, SEM_BF16_MFMA, SEM_FP16_MFMA); k: DEVICE [E][P] of the same type
+ * or NULL (k = 1); h2 >= 0.  w must not alias u. */
 sem_status sem_ax(const sem_mesh* mesh, const void* u, void* w, const void* k, double h2,
                   sem_prec prec, void* stream);
 
@@ -187,8 +194,9 @@ sem_status sem_jacobi_inverse(const sem_mesh* mesh, const double* k, double h2, 
  * the assembled operator, S = Jacobi (Sec. 2.2 names this acceleration;
  * recurrence of Lottes 2022).  r, z: DEVICE double [E][P] copy-consistent
  * (values at Dirichlet copies ignored / returned 0).  lmax > 0 is the bound
- * rho_hat.  prec: SEM_FP64 or SEM_FP32 (internal vectors and operator).
- * Stream-ordered. */
+ * rho_hat.  prec: SEM_FP64 (internal vectors and operator in double) or
+ * SEM_FP32 / SEM_BF16_MFMA / SEM_FP16_MFMA (float vectors; the operator's
+ * contractions per that precision).  Stream-ordered. */
 sem_status sem_cheb_apply(const sem_mesh* mesh, const double* r, double* z, const double* k,
                           double h2, int32_t order, double lmax, sem_prec prec, void* stream);
 

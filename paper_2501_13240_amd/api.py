@@ -133,13 +133,21 @@ def _prec_of(t):
     return L.PREC["fp64"] if t.dtype == torch.float64 else L.PREC["fp32"]
 
 
-def ax(mesh: Mesh, u, k=None, h2: float = 0.0, out=None):
-    """w = A_L(k) u on every element (sem_ax); precision from u's dtype."""
+def ax(mesh: Mesh, u, k=None, h2: float = 0.0, out=None, prec: str | None = None):
+    """w = A_L(k) u on every element (sem_ax).  prec: None (from u's dtype),
+    or 'bf16_mfma' / 'fp16_mfma' for float32 u (16-bit contraction operands)."""
     mesh.check_local(u, u.dtype, "u")
     if k is not None:
         mesh.check_local(k, u.dtype, "k")
+    if prec is None:
+        code = _prec_of(u)
+    else:
+        code = L.PREC[prec]
+        want = torch.float64 if prec == "fp64" else torch.float32
+        if u.dtype != want:
+            raise TypeError(f"precision {prec} takes {want} data, got {u.dtype}")
     w = torch.empty_like(u) if out is None else mesh.check_local(out, u.dtype, "out")
-    _check(mesh._lib.sem_ax(mesh.handle, _ptr(u), _ptr(w), _ptr(k), float(h2), _prec_of(u),
+    _check(mesh._lib.sem_ax(mesh.handle, _ptr(u), _ptr(w), _ptr(k), float(h2), code,
                             _stream()), "sem_ax")
     return w
 

@@ -181,7 +181,11 @@ static sem_status estimate_lmax(const sem_mesh* m, SolveWork& W, const double* k
   return SEM_OK;
 }
 
-static bool prec_ok(sem_prec p) { return p == SEM_FP64 || p == SEM_FP32; }
+static bool prec_ok(sem_prec p) {
+  return p == SEM_FP64 || p == SEM_FP32 || p == SEM_BF16_MFMA || p == SEM_FP16_MFMA;
+}
+// 16-bit contraction mode of an FP32-data precision
+static int lp_of(sem_prec p) { return p == SEM_BF16_MFMA ? 1 : p == SEM_FP16_MFMA ? 2 : 0; }
 
 static sem_status check_mesh(const sem_mesh* m) {
   if (!m) return fail(SEM_EINVAL, "mesh is NULL");
@@ -350,7 +354,9 @@ sem_status sem_ax(const sem_mesh* m, const void* u, void* w, const void* k, doub
     e = launch_ax<float>(m, (const float*)u, nullptr, (float*)w, (const float*)k, (float)h2,
                          m->G32.as<float>(), m->B32.as<float>(), m->D32.as<float>(), s);
   } else if (prec == SEM_BF16_MFMA || prec == SEM_FP16_MFMA) {
-    return fail(SEM_ENOTSUP, "matrix-core precisions are not available for sem_ax in this build");
+    e = launch_ax<float>(m, (const float*)u, nullptr, (float*)w, (const float*)k, (float)h2,
+                         m->G32.as<float>(), m->B32.as<float>(), m->D32.as<float>(), s, nullptr,
+                         lp_of(prec));
   } else {
     return fail(SEM_EINVAL, "unknown precision");
   }
@@ -417,7 +423,7 @@ sem_status sem_cheb_apply(const sem_mesh* m, const double* r, double* z, const d
   if (order < 1) return fail(SEM_EINVAL, "order must be >= 1");
   if (!(lmax > 0.0) || !std::isfinite(lmax)) return fail(SEM_EINVAL, "lmax must be > 0");
   if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
-  if (!prec_ok(prec)) return fail(SEM_ENOTSUP, "sem_cheb_apply supports SEM_FP64 and SEM_FP32");
+  if (!prec_ok(prec)) return fail(SEM_EINVAL, "unknown precision");
   hipStream_t s = (hipStream_t)stream;
   SolveWork& W = work_of(m);
   sem_status st = W.init(m, 1);
@@ -433,6 +439,7 @@ sem_status sem_cheb_apply(const sem_mesh* m, const double* r, double* z, const d
   } else {
     Op<float> o32;
     if ((st = op32_of(m, W, k, h2, s, o32))) return st;
+    o32.lp = lp_of(prec);
     st = cheb_apply_dev<double, float>(m, W, o32, W.dinv32.as<float>(), rf, zf, order, lmax,
                                        ChebCg(), s, nullptr);
   }
@@ -471,10 +478,10 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
   if (opts.mode == SEM_SOLVE_MIXED_IR && !(opts.inner_rtol > 0.0 && opts.inner_rtol < 1.0))
     return fail(SEM_EINVAL, "inner_rtol must be in (0, 1)");
   if (opts.precond == SEM_PRECOND_CHEBYSHEV && !prec_ok((sem_prec)opts.precond_prec))
-    return fail(SEM_ENOTSUP, "Chebyshev precision must be SEM_FP64 or SEM_FP32");
+    return fail(SEM_EINVAL, "unknown Chebyshev precision");
   if (opts.mode == SEM_SOLVE_MIXED_IR && opts.precond == SEM_PRECOND_CHEBYSHEV &&
-      opts.precond_prec != SEM_FP32)
-    return fail(SEM_EINVAL, "the inner solve of MIXED_IR runs in SEM_FP32");
+      opts.precond_prec == SEM_FP64)
+    return fail(SEM_EINVAL, "the inner solve of MIXED_IR runs in FP32 data");
 
   hipStream_t s = (hipStream_t)stream;
   SolveWork& W = work_of(m);
@@ -517,6 +524,8 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
   const Op<double> op64 = op64_of(m, k, h2);
   Op<float> op32;
   if ((st = op32_of(m, W, k, h2, s, op32))) return st;
+  Op<float> opc = op32;  // the Chebyshev preconditioner's FP32-data operator
+  opc.lp = lp_of((sem_prec)opts.precond_prec);
   const double* dinv = W.dinv.as<double>();
   const float* dinv32 = W.dinv32.as<float>();
 
@@ -547,9 +556,9 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
           return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, cg, ss, ap);
         };
       } else {
-        a.cheb = [op32, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                             double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, float>(mm, WW, op32, dinv32, r, z, order, lmax, cg, ss, ap);
+        a.cheb = [opc, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
+                                            double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
+          return cheb_apply_dev<double, float>(mm, WW, opc, dinv32, r, z, order, lmax, cg, ss, ap);
         };
       }
     }
@@ -588,9 +597,9 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     a.cheb_order = opts.cheb_order;
     if (cheb) {
       const int order = opts.cheb_order;
-      a.cheb = [op32, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const float* rr,
-                                           float* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-        return cheb_apply_dev<float, float>(mm, WW, op32, dinv32, rr, z, order, lmax, cg, ss, ap);
+      a.cheb = [opc, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const float* rr,
+                                          float* z, const ChebCg& cg, hipStream_t ss, int* ap) {
+        return cheb_apply_dev<float, float>(mm, WW, opc, dinv32, rr, z, order, lmax, cg, ss, ap);
       };
     }
     a.neumann = neumann;

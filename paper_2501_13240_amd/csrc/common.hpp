@@ -172,10 +172,12 @@ namespace sem {
 // element operator, FP64/FP32; `lmap` != nullptr: gather the input from a
 // free-unique vector (x_L = x[lmap], 0 where lmap < 0)
 // `skip` (device, nullable): nonzero -> the kernel returns at once
+// `lp` (FP32 only): 0 FP32 contractions, 1 bfloat16 and 2 half operands on
+// the matrix cores (hipErrorInvalidValue for other values or FP64 with lp != 0)
 template <typename T>
 hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
                      const T* G, const T* B, const T* D, hipStream_t s,
-                     const int32_t* skip = nullptr);
+                     const int32_t* skip = nullptr, int lp = 0);
 hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
                           hipStream_t s);
 template <typename T>

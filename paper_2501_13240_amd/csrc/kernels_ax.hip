@@ -24,6 +24,10 @@
 //
 // Per local point the FP64 apply streams u (8 B), six geometric factors
 // (48 B, planar layout [E][6][P]) and w (8 B): 64 B.
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace sem {
@@ -230,12 +234,97 @@ __device__ __forceinline__ void contract_tile(const T* __restrict__ src, T* __re
   }
 }
 
+typedef _Float16 v4h_t __attribute__((ext_vector_type(4)));
+typedef __bf16 v4bf_t __attribute__((ext_vector_type(4)));
+
+// 16x16x16 MFMA with 16-bit operands and FP32 accumulation (products of two
+// 16-bit values are exact in FP32): A[i][k] in lane i + 16 (k / 4), vector
+// element k % 4; B[k][j] in lane j + 16 (k / 4), element k % 4; result laid
+// out as in the FP32 16x16x4 form (checked on the device).  One instruction
+// covers a whole contraction: K = 16 >= N + 1, the rest padded with zeros.
+// LP = 1: bfloat16 operands; LP = 2: IEEE half operands.  Conversions round
+// to nearest, ties to even.
+template <int LP>
+struct Mfma16;
+template <>
+struct Mfma16<1> {
+  typedef v4bf_t V;
+  static __device__ __forceinline__ __bf16 cvt(float x) { return (__bf16)x; }
+  static __device__ __forceinline__ v4f_t mma(V a, V b, v4f_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma16<2> {
+  typedef v4h_t V;
+  static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
+  static __device__ __forceinline__ v4f_t mma(V a, V b, v4f_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// contract_tile with 16-bit operands: each source value is multiplied by the
+// block scale `sc` (a power of two, exact) before rounding, and each result
+// by `inv` = 1 / sc after accumulation.
+template <int n1, int LP, int DIR, bool ACC>
+__device__ __forceinline__ void contract_tile16(const float* __restrict__ src,
+                                                float* __restrict__ dst,
+                                                typename Mfma16<LP>::V afrag, int tile, int lane,
+                                                float sc, float inv) {
+  constexpr int P2 = n1 * n1;
+  const int col = tile * 16 + (lane & 15);
+  const int kk = lane >> 4;
+  const bool cval = col < P2;
+  const int c1 = cval ? col / n1 : 0, c0 = cval ? col % n1 : 0;
+  typename Mfma16<LP>::V b;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = 4 * kk + e;
+    float x = 0.0f;
+    if (cval && l < n1) {
+      const int a = DIR == 0 ? c1 * P2 + c0 * n1 + l : DIR == 1 ? c1 * P2 + l * n1 + c0 : l * P2 + col;
+      x = src[a];
+    }
+    b[e] = Mfma16<LP>::cvt(x * sc);
+  }
+  v4f_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  acc = Mfma16<LP>::mma(afrag, b, acc);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 4 * (lane >> 4) + r;
+    if (cval && row < n1) {
+      const int a =
+          DIR == 0 ? c1 * P2 + c0 * n1 + row : DIR == 1 ? c1 * P2 + row * n1 + c0 : row * P2 + col;
+      if (ACC) dst[a] += acc[r] * inv;
+      else dst[a] = acc[r] * inv;
+    }
+  }
+}
+
+// Power-of-two scale that puts a block maximum m in [2^14, 2^15) (IEEE half
+// keeps all its bits there and cannot overflow), with the exponent kept in
+// FP32's normal range; 1 for zero or non-finite m.
+__device__ __forceinline__ float half_block_scale(float m) {
+  if (!(m > 0.0f) || !(m <= 3.402823466e38f)) return 1.0f;
+  int ex;
+  (void)frexpf(m, &ex);
+  const int k = min(max(15 - ex, -126), 126);
+  return ldexpf(1.0f, k);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
 template <int N>
 struct MShape {
   static constexpr int n1 = N + 1;
   static constexpr int P2 = n1 * n1;
   static constexpr int P = P2 * n1;
-  static constexpr int TPB = P <= 729 ? 256 : 512;   // threads per element (= per workgroup)
+  static constexpr int TPB =                          // threads per element (= per workgroup)
+      P <= 64 ? 64 : P <= 128 ? 128 : P <= 729 ? 256 : 512;
   static constexpr int PPT = (P + TPB - 1) / TPB;    // points per thread
   static constexpr int NT = (P2 + 15) / 16;          // 16-column tiles per direction
   static constexpr int KS = (n1 + 3) / 4;            // K steps of 4
@@ -246,7 +335,11 @@ struct MShape {
 // Phases: loads -> forward contractions (3 NT tiles over the wavefronts) ->
 // pointwise metric and k -> transposed contractions accumulated direction
 // by direction into the (now free) input block -> stores.
-template <int N, typename T, bool GATHER>
+// LP = 0: contractions in T (FP64 or FP32 MFMA).  LP = 1 / 2 (T = float):
+// bfloat16 / half operands for D, the u block and each v_a block, FP32
+// accumulation; for half each block is scaled by its power-of-two block
+// scale, whose maxima are reduced before the barriers the phases already have.
+template <int N, typename T, bool GATHER, int LP>
 __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
     const T* __restrict__ u, const int32_t* __restrict__ lmap, T* __restrict__ w,
     const T* __restrict__ kf, const T h2, const T* __restrict__ G, const T* __restrict__ B,
@@ -254,9 +347,12 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
   using S = MShape<N>;
   constexpr int n1 = S::n1, P = S::P, TPB = S::TPB, PPT = S::PPT, NT = S::NT, KS = S::KS,
                 NW = S::NW;
+  static_assert(LP == 0 || std::is_same<T, float>::value, "16-bit operands need FP32 data");
+  constexpr bool kScale = LP == 2;
   if (skip && *skip) return;  // uniform over the grid
   __shared__ T su[P];
   __shared__ T sa[3][P];
+  __shared__ float smax[4][NW];  // block maxima of u, v_r, v_s, v_t per wavefront (LP = 2)
   T* so = su;  // output accumulator, reuses the input block after the forward phase
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t e = blockIdx.x;
@@ -282,16 +378,39 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
     for (int c = 0; c < 6; ++c) gq[s][c] = ld_stream(g + c * P);
     kq[s] = use_k ? ld_stream(kf + idx) : T(1);
   }
+  // derivative-matrix fragments: forward A = D, transposed A = D^T
   T af[KS], at[KS];
+  typename Mfma16<LP == 0 ? 1 : LP>::V af16, at16;
   {
     const int row = lane & 15, kk = lane >> 4;
+    if constexpr (LP == 0) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int l = 4 * s + kk;
-      const bool ok = row < n1 && l < n1;
-      af[s] = ok ? D[row * n1 + l] : T(0);
-      at[s] = ok ? D[l * n1 + row] : T(0);
+      for (int s = 0; s < KS; ++s) {
+        const int l = 4 * s + kk;
+        const bool ok = row < n1 && l < n1;
+        af[s] = ok ? D[row * n1 + l] : T(0);
+        at[s] = ok ? D[l * n1 + row] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int l = 4 * kk + x;
+        const bool ok = row < n1 && l < n1;
+        af16[x] = Mfma16<LP>::cvt(ok ? D[row * n1 + l] : 0.0f);
+        at16[x] = Mfma16<LP>::cvt(ok ? D[l * n1 + row] : 0.0f);
+      }
     }
+  }
+  (void)af;
+  (void)at;
+  (void)af16;
+  (void)at16;
+  if constexpr (kScale) {
+    float mu = 0.0f;
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) mu = fmaxf(mu, fabsf((float)uq[s]));
+    mu = wave_max(mu);
+    if (lane == 0) smax[0][wv] = mu;
   }
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
@@ -299,13 +418,31 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
     if (q < P) su[q] = uq[s];
   }
   __syncthreads();
-  for (int job = wv; job < 3 * NT; job += NW) {
-    const int dir = job / NT, tile = job - dir * NT;
-    if (dir == 0) contract_tile<n1, T, 0, false>(su, sa[0], af, tile, lane);
-    else if (dir == 1) contract_tile<n1, T, 1, false>(su, sa[1], af, tile, lane);
-    else contract_tile<n1, T, 2, false>(su, sa[2], af, tile, lane);
+  if constexpr (LP == 0) {
+    for (int job = wv; job < 3 * NT; job += NW) {
+      const int dir = job / NT, tile = job - dir * NT;
+      if (dir == 0) contract_tile<n1, T, 0, false>(su, sa[0], af, tile, lane);
+      else if (dir == 1) contract_tile<n1, T, 1, false>(su, sa[1], af, tile, lane);
+      else contract_tile<n1, T, 2, false>(su, sa[2], af, tile, lane);
+    }
+  } else {
+    float sc = 1.0f;
+    if constexpr (kScale) {
+      float m = 0.0f;
+#pragma unroll
+      for (int x = 0; x < NW; ++x) m = fmaxf(m, smax[0][x]);
+      sc = half_block_scale(m);
+    }
+    const float inv = 1.0f / sc;
+    for (int job = wv; job < 3 * NT; job += NW) {
+      const int dir = job / NT, tile = job - dir * NT;
+      if (dir == 0) contract_tile16<n1, LP, 0, false>(su, sa[0], af16, tile, lane, sc, inv);
+      else if (dir == 1) contract_tile16<n1, LP, 1, false>(su, sa[1], af16, tile, lane, sc, inv);
+      else contract_tile16<n1, LP, 2, false>(su, sa[2], af16, tile, lane, sc, inv);
+    }
   }
   __syncthreads();
+  float mv[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
     const int q = t + s * TPB;
@@ -323,14 +460,47 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
       sa[0][q] = vr;
       sa[1][q] = vs;
       sa[2][q] = vt;
+      if constexpr (kScale) {
+        mv[0] = fmaxf(mv[0], fabsf((float)vr));
+        mv[1] = fmaxf(mv[1], fabsf((float)vs));
+        mv[2] = fmaxf(mv[2], fabsf((float)vt));
+      }
+    }
+  }
+  if constexpr (kScale) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float m = wave_max(mv[d]);
+      if (lane == 0) smax[1 + d][wv] = m;
     }
   }
   __syncthreads();
-  for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 0, false>(sa[0], so, at, tile, lane);
-  __syncthreads();
-  for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 1, true>(sa[1], so, at, tile, lane);
-  __syncthreads();
-  for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 2, true>(sa[2], so, at, tile, lane);
+  if constexpr (LP == 0) {
+    for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 0, false>(sa[0], so, at, tile, lane);
+    __syncthreads();
+    for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 1, true>(sa[1], so, at, tile, lane);
+    __syncthreads();
+    for (int tile = wv; tile < NT; tile += NW) contract_tile<n1, T, 2, true>(sa[2], so, at, tile, lane);
+  } else {
+    float sc[3] = {1.0f, 1.0f, 1.0f};
+    if constexpr (kScale) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float m = 0.0f;
+#pragma unroll
+        for (int x = 0; x < NW; ++x) m = fmaxf(m, smax[1 + d][x]);
+        sc[d] = half_block_scale(m);
+      }
+    }
+    for (int tile = wv; tile < NT; tile += NW)
+      contract_tile16<n1, LP, 0, false>(sa[0], so, at16, tile, lane, sc[0], 1.0f / sc[0]);
+    __syncthreads();
+    for (int tile = wv; tile < NT; tile += NW)
+      contract_tile16<n1, LP, 1, true>(sa[1], so, at16, tile, lane, sc[1], 1.0f / sc[1]);
+    __syncthreads();
+    for (int tile = wv; tile < NT; tile += NW)
+      contract_tile16<n1, LP, 2, true>(sa[2], so, at16, tile, lane, sc[2], 1.0f / sc[2]);
+  }
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
@@ -344,9 +514,26 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
   }
 }
 
-// which element-operator kernel serves order N: the matrix-core one from
-// N = 5 on (measured faster there), the scalar one below
-constexpr bool use_mfma(int N) { return N >= 5; }
+// The matrix-core kernel exists from N = 5 on (below that a 16-wide tile
+// wastes most of its lanes).  Which kernel serves a launch: the environment
+// variable SEM_AX_KERNEL = scalar | mfma forces one (read once per process),
+// otherwise the measured default of prefer_mfma.
+constexpr bool has_mfma(int N) { return N >= 5; }
+enum class AxChoice { Auto, Scalar, Mfma };
+AxChoice ax_choice() {
+  static const AxChoice c = [] {
+    const char* e = std::getenv("SEM_AX_KERNEL");
+    if (e && std::strcmp(e, "scalar") == 0) return AxChoice::Scalar;
+    if (e && std::strcmp(e, "mfma") == 0) return AxChoice::Mfma;
+    return AxChoice::Auto;
+  }();
+  return c;
+}
+bool prefer_mfma(int N, bool gather, bool fp32) {
+  (void)gather;
+  (void)fp32;
+  return N >= 5;
+}
 
 // kbar_q = sum_ab (D_a wbar)_q G_ab,q (D_b u)_q: the derivative of the
 // operator in k contracted with a cotangent (same mapping, 72 B per point).
@@ -416,18 +603,32 @@ __global__ void mass_kernel(int64_t n, const T* __restrict__ B, const T* __restr
     w[q] = B[q] * u[q];
 }
 
+template <int N, typename T, int LP>
+hipError_t run_ax_mfma(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
+                       const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip) {
+  using M = MShape<N>;
+  if (lmap)
+    hipLaunchKernelGGL((ax_mfma_kernel<N, T, true, LP>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                       u, lmap, w, k, h2, G, B, D, m->E, skip);
+  else
+    hipLaunchKernelGGL((ax_mfma_kernel<N, T, false, LP>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                       u, lmap, w, k, h2, G, B, D, m->E, skip);
+  return hipGetLastError();
+}
+
 template <int N, typename T>
 hipError_t run_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
-                  const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip) {
-  if constexpr (use_mfma(N)) {
-    using M = MShape<N>;
-    if (lmap)
-      hipLaunchKernelGGL((ax_mfma_kernel<N, T, true>), dim3((unsigned)m->E), dim3(M::TPB), 0, s, u,
-                         lmap, w, k, h2, G, B, D, m->E, skip);
-    else
-      hipLaunchKernelGGL((ax_mfma_kernel<N, T, false>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                         u, lmap, w, k, h2, G, B, D, m->E, skip);
-    return hipGetLastError();
+                  const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip, int lp) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (lp == 1) return run_ax_mfma<N, float, 1>(m, u, lmap, w, k, h2, G, B, D, s, skip);
+    if (lp == 2) return run_ax_mfma<N, float, 2>(m, u, lmap, w, k, h2, G, B, D, s, skip);
+  }
+  if (lp != 0) return hipErrorInvalidValue;
+  if constexpr (has_mfma(N)) {
+    const AxChoice c = ax_choice();
+    const bool mfma = c == AxChoice::Auto ? prefer_mfma(N, lmap != nullptr, sizeof(T) == 4)
+                                          : c == AxChoice::Mfma;
+    if (mfma) return run_ax_mfma<N, T, 0>(m, u, lmap, w, k, h2, G, B, D, s, skip);
   }
   using S = Shape<N>;
   const int64_t grid = (m->E + S::EPB - 1) / S::EPB;
@@ -454,27 +655,28 @@ hipError_t run_kbar(const sem_mesh* m, const double* u, const double* wb, double
 
 template <typename T>
 hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
-                     const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip) {
+                     const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip,
+                     int lp) {
   switch (m->N) {
-    case 1: return run_ax<1, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 2: return run_ax<2, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 3: return run_ax<3, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 4: return run_ax<4, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 5: return run_ax<5, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 6: return run_ax<6, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 7: return run_ax<7, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 8: return run_ax<8, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 9: return run_ax<9, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    case 10: return run_ax<10, T>(m, u, lmap, w, k, h2, G, B, D, s, skip);
+    case 1: return run_ax<1, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 2: return run_ax<2, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 3: return run_ax<3, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 4: return run_ax<4, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 5: return run_ax<5, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 6: return run_ax<6, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 7: return run_ax<7, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 8: return run_ax<8, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 9: return run_ax<9, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 10: return run_ax<10, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
     default: return hipErrorInvalidValue;
   }
 }
 template hipError_t launch_ax<double>(const sem_mesh*, const double*, const int32_t*, double*,
                                       const double*, double, const double*, const double*,
-                                      const double*, hipStream_t, const int32_t*);
+                                      const double*, hipStream_t, const int32_t*, int);
 template hipError_t launch_ax<float>(const sem_mesh*, const float*, const int32_t*, float*,
                                      const float*, float, const float*, const float*,
-                                     const float*, hipStream_t, const int32_t*);
+                                     const float*, hipStream_t, const int32_t*, int);
 
 hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
                           hipStream_t s) {

@@ -490,7 +490,8 @@ sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* x
     SEM_HIP(hipEventRecord(e0, s));
   }
   hipError_t e =
-      launch_ax<T>(m, xf, m->lmap.as<int32_t>(), wL, op.k, op.h2, op.G, op.B, op.D, s, op.skip);
+      launch_ax<T>(m, xf, m->lmap.as<int32_t>(), wL, op.k, op.h2, op.G, op.B, op.D, s, op.skip,
+                   op.lp);
   if (e != hipSuccess) return hip_fail(e, "operator kernel");
   if (timed) SEM_HIP(hipEventRecord(e1, s));
   return SEM_OK;

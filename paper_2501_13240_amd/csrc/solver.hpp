@@ -35,6 +35,7 @@ struct Op {
   const T* D = nullptr;
   T h2 = T(0);
   const int32_t* skip = nullptr;  // device flag: nonzero = skip the launch's work
+  int lp = 0;                     // FP32 only: 16-bit contraction operands (1 bf16, 2 half)
 };
 
 struct CgResult {
