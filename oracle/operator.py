@@ -131,13 +131,15 @@ def round_to_format(x, fmt):
 
 def block_scale(X, fmt):
     """Per-element power-of-two scale of a block X (E, P): 2^(15 - e) with
-    max|X| = f 2^e, f in [0.5, 1), for 'fp16'; 1 for 'bf16' and zero blocks."""
+    max|X| = f 2^e, f in [0.5, 1), for 'fp16', the exponent 15 - e limited to
+    [-126, 126] so the scale and its inverse are normal FP32 numbers; 1 for
+    'bf16' and zero blocks."""
     E = X.shape[0]
     if fmt != "fp16":
         return np.ones(E)
     m = np.max(np.abs(X.reshape(E, -1)), axis=1)
     _, ex = np.frexp(m)
-    return np.where(m > 0, np.ldexp(1.0, 15 - ex), 1.0)
+    return np.where(m > 0, np.ldexp(1.0, np.clip(15 - ex, -126, 126)), 1.0)
 
 
 def _round_block(X, fmt):

@@ -55,6 +55,9 @@ def test_block_scale_puts_block_maximum_in_range():
     assert np.all(np.log2(s) == np.round(np.log2(s)))
     assert s[7] == 1.0
     np.testing.assert_array_equal(block_scale(X, "bf16"), np.ones(50))
+    # the exponent stays in FP32's normal range for extreme blocks
+    ext = block_scale(np.array([[1e-38], [3e38]]), "fp16")
+    np.testing.assert_array_equal(ext, [2.0 ** 126, 2.0 ** -113])
 
 
 def _problem(N, shape=(2, 2, 4), scale=1.0, seed=13):
