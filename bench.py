@@ -45,6 +45,8 @@ def parse():
                     help="also run a plain 1 GiB device copy (for counter calibration)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-vs-FP64 solve comparison on the 32^3, N=9 Neumann box")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the small-case solves and the forward/backward timing")
     return ap.parse_args()
 
 
@@ -69,6 +71,14 @@ def cpu_baseline(iters):
                         f"32x8x16-element slice of the same recipe ({P.num.n} unique nodes), "
                         f"single-threaded einsum/bincount, {dt:.1f} s"),
                 seconds=dt)
+
+
+def ax_kernel_name(N):
+    """Which operator kernel the library launches at order N (the matrix-core
+    one from N = 5 on unless SEM_AX_KERNEL overrides)."""
+    if N < 5 or os.environ.get("SEM_AX_KERNEL", "") == "scalar":
+        return "ax_kernel"
+    return "ax_mfma_kernel"
 
 
 def counter_traffic():
@@ -122,6 +132,7 @@ def mixed_vs_fp64(sem):
         "fp64_jacobi_cg": dict(mode="cg", precond="jacobi"),
         "fp64_cheb3_fcg": dict(mode="cg", precond="chebyshev", precond_prec="fp64"),
         "fp64_cg_fp32_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="fp32"),
+        "fp64_cg_bf16_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="bf16_mfma"),
         "mixed_ir_fp32_cg": dict(mode="mixed_ir", precond="jacobi", precond_prec="fp32"),
     }
     out = {"workload": "32x32x32 hexahedra, N=9, tanh 1:20 z-clustering, seeded wall-preserving "
@@ -140,6 +151,101 @@ def mixed_vs_fp64(sem):
     out["fastest_mixed"] = best
     if best:
         out["speedup_vs_fp64"] = out["fp64_jacobi_cg"]["ms"] / out[best]["ms"]
+    M.close()
+    return out
+
+
+def gs_rate(sem, M, reps):
+    """sem_gs on the benchmark mesh: 20 B per local copy of a shared node
+    (index 4, read 8, write 8) + 4 B per shared node (segment offset)."""
+    import torch
+
+    mult = M.multiplicity()
+    shared = mult > 1
+    copies = int(shared.sum())
+    nodes = float((1.0 / mult[shared]).sum())
+    alg = 20.0 * copies + 4.0 * nodes
+    v = torch.randn(M.E, M.P, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        sem.gs(M, v)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sem.gs(M, v)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    return {"us": us, "algorithmic_bytes": alg, "gb_s": alg / us / 1e3,
+            "shared_copies": copies}
+
+
+def small_solves(sem):
+    """Time to ||b - A x|| <= 1e-10 ||b|| on the 4^3-element unit cube at
+    N = 7 and 9 (manufactured right-hand side): launch-bound cases, the
+    variants differ by iteration counts, not bandwidth."""
+    import torch
+    from sem_inputs import config_mesh
+
+    variants = {
+        "fp64_jacobi_cg": dict(mode="cg", precond="jacobi"),
+        "fp64_cheb3_fcg": dict(mode="cg", precond="chebyshev", precond_prec="fp64"),
+        "fp64_cg_fp32_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="fp32"),
+        "fp64_cg_bf16_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="bf16_mfma"),
+        "fp64_cg_fp16_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="fp16_mfma"),
+        "mixed_ir_fp32_cg": dict(mode="mixed_ir", precond="jacobi", precond_prec="fp32"),
+        "mixed_ir_fp32_cheb3": dict(mode="mixed_ir", precond="chebyshev", precond_prec="fp32"),
+    }
+    out = {}
+    for N in (7, 9):
+        m, fld = config_mesh(1, N=N)
+        M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+        f = torch.tensor(fld["f"] * 3 * np.pi ** 2, device="cuda")
+        b = sem.gs(M, sem.mass(M, f))
+        sem.lmax_estimate(M)
+        res = {"n_unique": M.info["n_unique"]}
+        for name, v in variants.items():
+            sem.solve(M, b, rtol=1e-10, **v)  # warm (graph capture, work space)
+            best = None
+            for _ in range(3):
+                x, st = sem.solve(M, b, rtol=1e-10, **v)
+                if best is None or st["time_ms"] < best[1]["time_ms"]:
+                    best = (x, st)
+            x, st = best
+            res[name] = {"ms": st["time_ms"], "iters": st["iters"], "outer": st["outer_iters"],
+                         "true_rel_res": true_rel_residual(sem, M, b, x)}
+        out[f"N{N}"] = res
+        M.close()
+    return out
+
+
+def gradient_timing(sem):
+    """Forward solve and backward (adjoint solve + k-contraction) on the
+    16^3-element, N = 7 variable-coefficient Helmholtz cube, both to 1e-12."""
+    import torch
+    from sem_inputs import config_mesh
+
+    m, fld = config_mesh(4)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    f = torch.tensor(fld["f"], device="cuda")
+    b = sem.gs(M, sem.mass(M, f))
+    target = f / (3 * np.pi ** 2 + 1.0)
+    free = M.multiplicity()
+    w = torch.where(sem.mask(M, torch.ones_like(f)) > 0, 1.0 / free, torch.zeros_like(f))
+    k0 = torch.tensor(fld["k"], device="cuda")
+    out = {}
+    for rep in range(2):
+        k = k0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = sem.sem_solve(M, b, k=k, h2=fld["h2"], rtol=1e-12)
+        loss = torch.sum(w * (x - target) ** 2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out = {"forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+               "n_unique": M.info["n_unique"]}
     M.close()
     return out
 
@@ -207,6 +313,9 @@ def main():
     sem_ax_ms = e0.elapsed_time(e1) / args.ax_reps
     log(f"sem_ax: {sem_ax_ms * 1e3:.1f} us, {64.0 * nL / sem_ax_ms / 1e6:.0f} GB/s")
 
+    gs = gs_rate(sem, M, args.ax_reps)
+    log(f"sem_gs: {gs['us']:.1f} us, {gs['gb_s']:.0f} GB/s")
+
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -243,17 +352,26 @@ def main():
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": counter_traffic(),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": "ax_kernel<7,double,gather> (element operator, 64 B/local point)",
+            "kernel": f"{ax_kernel_name(M.N)}<{M.N},double,gather> (element operator, 64 B/local point)",
             "avg_launch_us": ax_avg_ms * 1e3,
             "launches_timed": ax_n,
         },
         "ax_gdof_s": n_unique / (sem_ax_ms * 1e-3) / 1e9,
         "ax_us": sem_ax_ms * 1e3,
+        "ax_hbm_frac": 64.0 * nL / (sem_ax_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "gs": gs,
     }
+    if not args.no_extras:
+        M.close()
+        log("small solves (4^3 unit cube, N = 7 and 9) ...")
+        out["small_solves"] = small_solves(sem)
+        log("forward/backward on the 16^3 Helmholtz cube ...")
+        out["gradient"] = gradient_timing(sem)
     if not args.no_mixed:
         log("mixed vs FP64 on the 32^3, N=9 Neumann box ...")
         M.close()
         out["mixed_vs_fp64"] = mixed_vs_fp64(sem)
+    M.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb = cpu_baseline(args.cpu_sample_iters)
