@@ -20,7 +20,9 @@ definitions in order:
 * ``solvers``   Jacobi-preconditioned conjugate gradients (the pressure Poisson
                 solve, Sec. 2.2), fourth-kind Chebyshev acceleration
                 (Sec. 2.2), CG-Lanczos eigenvalue bound, null-space projection;
-* ``grad``      the adjoint gradient of a solve with respect to k and b.
+* ``grad``      the adjoint gradient of a solve with respect to k and b;
+* ``pmg``       the p-multigrid preconditioner with Chebyshev smoothing (the
+                default pressure preconditioner named in Sec. 2.2).
 
 The paper names the method but prints none of its formulas; every function
 states the textbook definition it follows and each is pinned by a test under
@@ -33,6 +35,7 @@ from .operator import (local_apply, local_diagonal, mass_apply, kgrad_contractio
                        local_apply_lowprec, local_apply_majorant, round_to_format, block_scale)
 from .assembly import Numbering, explicit_matrix, element_matrices
 from .solvers import Problem, pcg, chebyshev_apply, lanczos_lmax
+from .pmg import PMG, coarse_mesh, interpolation_matrix, level_orders
 from .grad import solve_and_adjoint_gradient
 
 __all__ = [
@@ -57,4 +60,8 @@ __all__ = [
     "chebyshev_apply",
     "lanczos_lmax",
     "solve_and_adjoint_gradient",
+    "PMG",
+    "coarse_mesh",
+    "interpolation_matrix",
+    "level_orders",
 ]
