@@ -92,7 +92,14 @@ typedef struct {
   int32_t has_nullspace; /* 1 if no Dirichlet node: the constant is in the kernel for h2 = 0 */
 } sem_mesh_info;
 
-typedef enum { SEM_PRECOND_JACOBI = 0, SEM_PRECOND_CHEBYSHEV = 1 } sem_precond;
+/* Preconditioner of the CG.  SEM_PRECOND_PMG: one p-multigrid V-cycle per
+ * iteration (Sec. 2.2: the default pressure preconditioner, p-multigrid with
+ * fourth-kind Chebyshev-accelerated smoothing); needs sem_setup_pmg first. */
+typedef enum {
+  SEM_PRECOND_JACOBI = 0,
+  SEM_PRECOND_CHEBYSHEV = 1,
+  SEM_PRECOND_PMG = 2
+} sem_precond;
 typedef enum { SEM_SOLVE_CG = 0, SEM_SOLVE_MIXED_IR = 1 } sem_solve_mode;
 
 typedef struct {
@@ -103,7 +110,8 @@ typedef struct {
   int32_t precond;      /* sem_precond of the CG (mode CG) or of the inner CG (MIXED_IR) */
   int32_t precond_prec; /* sem_prec of the Chebyshev preconditioner.  Mode CG: any (FP64 CG with
                            a lower-precision preconditioner); MIXED_IR: SEM_FP32, SEM_BF16_MFMA
-                           or SEM_FP16_MFMA (the inner CG's own operator stays FP32) */
+                           or SEM_FP16_MFMA (the inner CG's own operator stays FP32).
+                           Multigrid: SEM_FP32 (the cycle in float) or, in mode CG, SEM_FP64 */
   int32_t cheb_order;   /* Chebyshev order m >= 1 (m-1 operator applies per call); default 3 */
   double lmax;          /* Chebyshev bound rho_hat >= lambda_max(D^-1 A); <= 0: 1.1 x a
                            20-step CG-Lanczos estimate (cached per mesh for k == NULL) */
@@ -225,6 +233,62 @@ sem_status sem_pcg_solve(const sem_mesh* mesh, const double* b, double* x, const
  * so that <wbar, A_L(dk) u> = <kbar, dk>.  Stream-ordered. */
 sem_status sem_ax_backward(const sem_mesh* mesh, const double* u, const double* wbar,
                            const double* k, double h2, double* ubar, double* kbar, void* stream);
+
+/* ---------------------------------------------------------- p-multigrid
+ * Levels of polynomial order N_0 = N > N_1 > ... > N_L on the same hexahedra
+ * (default N, floor(N/2), ..., 1).  Level l >= 1 is a mesh of its own: its
+ * element maps interpolate the fine ones at the order-N_l GLL points and its
+ * unknowns are identified through the fine global ids (a coarse node is a
+ * mesh vertex, a position on a mesh edge or face, or an element-interior
+ * position), so every level has the spectral-element operator of its order.
+ * One V-cycle: pre-smoothing x = C_l(r), coarse correction
+ * x += P_l V_{l+1}(P_l^T (r - A_l x)), post-smoothing x += C_l(r - A_l x),
+ * with C_l the fourth-kind Chebyshev-Jacobi polynomial of order smooth_order
+ * (bound 1.1 x a 20-step CG-Lanczos estimate per level, per solve), P_l the
+ * element-wise tensor-product Lagrange interpolation (averaged over the copies
+ * of a fine node), P_l^T its transpose, and coarse_iters Jacobi-PCG
+ * iterations from zero on the coarsest level (constant mode projected out on
+ * a singular level).  Sec. 2.2 names this preconditioner family (with
+ * overlapping Schwarz smoothers, not built here: the smoother is Jacobi). */
+#define SEM_PMG_MAX_LEVELS 8
+typedef struct {
+  int32_t n_levels;                    /* 0: default orders; else the number of entries used */
+  int32_t orders[SEM_PMG_MAX_LEVELS];  /* strictly decreasing, orders[0] = N, all >= 1 */
+  int32_t smooth_order;                /* Chebyshev order m >= 1 (m-1 applies per smoothing) */
+  int32_t coarse_iters;                /* Jacobi-PCG iterations on the coarsest level, >= 1 */
+} sem_pmg_opts;
+
+/* Defaults: n_levels 0, smooth_order 3, coarse_iters 30. */
+void sem_pmg_opts_default(sem_pmg_opts* opts);
+
+/* Build (or rebuild) the hierarchy of `mesh` from the description it was set
+ * up with (same N and E; HOST arrays, read during the call only).  The coarse
+ * meshes are owned by `mesh` and freed with it.  Blocks.  SEM_EINVAL for bad
+ * options, a different description, or a mesh whose edge or face has corners
+ * sharing a global id (one element across a periodic direction). */
+sem_status sem_setup_pmg(sem_mesh* mesh, const sem_mesh_desc* desc, const sem_pmg_opts* opts,
+                         void* stream);
+
+/* Level orders (HOST int32[SEM_PMG_MAX_LEVELS], nullable) and the Chebyshev
+ * bounds of the last solve or apply (HOST double[SEM_PMG_MAX_LEVELS],
+ * nullable; 0 before the first). */
+sem_status sem_pmg_info(const sem_mesh* mesh, int32_t* n_levels, int32_t* orders,
+                        double* rho_hat);
+
+/* z = V(r): one V-cycle for A(k) (+ h2 B).  r, z: DEVICE double [E][P]
+ * copy-consistent (values at Dirichlet copies ignored / returned 0); k DEVICE
+ * double [E][P] or NULL.  prec: SEM_FP64 or SEM_FP32 (arithmetic of the
+ * cycle).  Blocks on the first call for given k, h2 (level bounds). */
+sem_status sem_pmg_apply(const sem_mesh* mesh, const double* r, double* z, const double* k,
+                         double h2, sem_prec prec, void* stream);
+
+/* HOST-only.  The order-Nc mesh sem_setup_pmg builds from an order-N one
+ * (2 <= N <= 10, 1 <= Nc < N): xyz_c [E][Pc][3] (nullable together with
+ * xyz), gid_c [E][Pc] (ids 0.., numbered per coarse node), dirichlet_c
+ * [E][Pc] (NULL together with dirichlet), all caller-allocated. */
+sem_status sem_host_coarse_mesh(int32_t N, int64_t E, const int64_t* gid,
+                                const uint8_t* dirichlet, const double* xyz, int32_t Nc,
+                                int64_t* gid_c, uint8_t* dirichlet_c, double* xyz_c);
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* sem_last_error(void);

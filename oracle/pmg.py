@@ -186,7 +186,7 @@ class PMG:
     """The level hierarchy and the V-cycle (FP64)."""
 
     def __init__(self, xyz, gid, dirichlet, N, k=None, h2=0.0, orders=None, smooth_order=3,
-                 coarse_iters=30, coarse="cg"):
+                 coarse_iters=30, coarse="cg", rho=None):
         self.orders = level_orders(N) if orders is None else list(orders)
         self.m = smooth_order
         self.coarse_iters = coarse_iters
@@ -202,11 +202,14 @@ class PMG:
         self.J = [interpolation_matrix(self.orders[l + 1], self.orders[l])
                   for l in range(len(self.orders) - 1)]
         self.dinv = [1.0 / P.diag() for P in self.levels]
-        self.rho = []
-        for l, P in enumerate(self.levels):
-            proj = P.project if P.neumann else None
-            v0 = np.random.default_rng(7 + l).standard_normal(P.num.n_free)
-            self.rho.append(1.1 * lanczos_lmax(P.apply, self.dinv[l], v0, 20, proj))
+        if rho is not None:  # given bounds (e.g. another implementation's estimates)
+            self.rho = [float(v) for v in rho]
+        else:
+            self.rho = []
+            for l, P in enumerate(self.levels):
+                proj = P.project if P.neumann else None
+                v0 = np.random.default_rng(7 + l).standard_normal(P.num.n_free)
+                self.rho.append(1.1 * lanczos_lmax(P.apply, self.dinv[l], v0, 20, proj))
         if coarse == "exact":
             from .assembly import explicit_matrix
             Pc = self.levels[-1]

@@ -17,11 +17,13 @@ from .api import (
     cheb_apply,
     gll,
     gs,
+    host_coarse_mesh,
     host_numbering,
     jacobi_inverse,
     lmax_estimate,
     mask,
     mass,
+    pmg_apply,
     solve,
 )
 from .autograd import SemSolve, sem_solve
@@ -39,11 +41,13 @@ __all__ = [
     "cheb_apply",
     "gll",
     "gs",
+    "host_coarse_mesh",
     "host_numbering",
     "jacobi_inverse",
     "lmax_estimate",
     "mask",
     "mass",
+    "pmg_apply",
     "solve",
     "SemSolve",
     "sem_solve",

@@ -23,7 +23,8 @@ SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EDEVICE, SEM_ENOCONV, SEM_EBREAKDOWN, SEM_EN
 STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_ENOMEM", -3: "SEM_EDEVICE",
                 -4: "SEM_ENOCONV", -5: "SEM_EBREAKDOWN", -6: "SEM_ENOTSUP"}
 PREC = {"fp64": 0, "fp32": 1, "bf16_mfma": 2, "fp16_mfma": 3}
-PRECOND = {"jacobi": 0, "chebyshev": 1}
+PRECOND = {"jacobi": 0, "chebyshev": 1, "pmg": 2}
+PMG_MAX_LEVELS = 8
 MODE = {"cg": 0, "mixed_ir": 1}
 
 
@@ -53,6 +54,11 @@ class SolveStats(ctypes.Structure):
                 ("pad_", c_int32)]
 
 
+class PmgOpts(ctypes.Structure):
+    _fields_ = [("n_levels", c_int32), ("orders", c_int32 * 8), ("smooth_order", c_int32),
+                ("coarse_iters", c_int32)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "sem_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
@@ -70,6 +76,14 @@ SIGNATURES = {
     "sem_jacobi_inverse": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "sem_cheb_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
                                  c_double, c_int32, c_void_p]),
+    "sem_pmg_opts_default": (None, [ctypes.POINTER(PmgOpts)]),
+    "sem_setup_pmg": (c_int32, [c_void_p, ctypes.POINTER(MeshDesc), ctypes.POINTER(PmgOpts),
+                                c_void_p]),
+    "sem_pmg_info": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sem_pmg_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
+                                c_void_p]),
+    "sem_host_coarse_mesh": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_int32,
+                                       c_void_p, c_void_p, c_void_p]),
     "sem_lmax_estimate": (c_int32, [c_void_p, c_void_p, c_double, c_int32,
                                     ctypes.POINTER(c_double), c_void_p]),
     "sem_pcg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,

@@ -77,6 +77,9 @@ class Mesh:
         if gid.size != self.E * self.P or xyz.size != 3 * gid.size:
             raise ValueError("xyz must be (E, P, 3) and gid (E, P) with P = (N+1)^3")
         d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        # kept for a later sem_setup_pmg (it re-reads the description)
+        self._desc_arrays = (xyz, gid, d)
+        self._pmg = False
         desc = L.MeshDesc(self.N, self.E, _np_ptr(xyz), _np_ptr(gid), _np_ptr(d))
         h = ctypes.c_void_p()
         self.device = torch.cuda.current_device()
@@ -91,6 +94,32 @@ class Mesh:
     @property
     def handle(self):
         return self._h
+
+    def setup_pmg(self, orders=None, smooth_order: int = 3, coarse_iters: int = 30):
+        """Build the p-multigrid hierarchy (sem_setup_pmg); orders default to
+        N, N//2, ..., 1."""
+        opts = L.PmgOpts()
+        self._lib.sem_pmg_opts_default(ctypes.byref(opts))
+        if orders is not None:
+            orders = [int(o) for o in orders]
+            opts.n_levels = len(orders)
+            for i, o in enumerate(orders):
+                opts.orders[i] = o
+        opts.smooth_order = int(smooth_order)
+        opts.coarse_iters = int(coarse_iters)
+        xyz, gid, d = self._desc_arrays
+        desc = L.MeshDesc(self.N, self.E, _np_ptr(xyz), _np_ptr(gid), _np_ptr(d))
+        _check(self._lib.sem_setup_pmg(self._h, ctypes.byref(desc), ctypes.byref(opts), _stream()),
+               "sem_setup_pmg")
+        self._pmg = True
+
+    def pmg_info(self):
+        """(level orders, Chebyshev bounds of the last solve or apply)."""
+        n = ctypes.c_int32()
+        orders = (ctypes.c_int32 * L.PMG_MAX_LEVELS)()
+        rho = (ctypes.c_double * L.PMG_MAX_LEVELS)()
+        _check(self._lib.sem_pmg_info(self._h, ctypes.byref(n), orders, rho), "sem_pmg_info")
+        return list(orders[:n.value]), list(rho[:n.value])
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -190,6 +219,36 @@ def cheb_apply(mesh: Mesh, r, lmax: float, k=None, h2: float = 0.0, order: int =
     return z
 
 
+def pmg_apply(mesh: Mesh, r, k=None, h2: float = 0.0, prec: str = "fp32"):
+    """z = V(r), one p-multigrid V-cycle (sem_pmg_apply); sets up the default
+    hierarchy on first use."""
+    mesh.check_local(r, torch.float64, "r")
+    mesh.check_local(k, torch.float64, "k")
+    if not mesh._pmg:
+        mesh.setup_pmg()
+    z = torch.empty_like(r)
+    _check(mesh._lib.sem_pmg_apply(mesh.handle, _ptr(r), _ptr(z), _ptr(k), float(h2),
+                                   L.PREC[prec], _stream()), "sem_pmg_apply")
+    return z
+
+
+def host_coarse_mesh(N: int, gid: np.ndarray, dirichlet, xyz, Nc: int):
+    """The library's order-Nc mesh on the hexahedra of an order-N mesh (host)."""
+    lib = L.load()
+    gid = np.ascontiguousarray(gid, dtype=np.int64)
+    E = gid.shape[0]
+    Pc = (Nc + 1) ** 3
+    d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    x = None if xyz is None else np.ascontiguousarray(xyz, dtype=np.float64)
+    gid_c = np.empty((E, Pc), dtype=np.int64)
+    d_c = None if d is None else np.empty((E, Pc), dtype=np.uint8)
+    x_c = None if x is None else np.empty((E, Pc, 3), dtype=np.float64)
+    _check(lib.sem_host_coarse_mesh(N, E, _np_ptr(gid), _np_ptr(d), _np_ptr(x), Nc,
+                                    _np_ptr(gid_c), _np_ptr(d_c), _np_ptr(x_c)),
+           "sem_host_coarse_mesh")
+    return x_c, gid_c, d_c
+
+
 def lmax_estimate(mesh: Mesh, k=None, h2: float = 0.0, steps: int = 20) -> float:
     mesh.check_local(k, torch.float64, "k")
     out = ctypes.c_double()
@@ -199,7 +258,7 @@ def lmax_estimate(mesh: Mesh, k=None, h2: float = 0.0, steps: int = 20) -> float
 
 
 def solve(mesh: Mesh, b, x0=None, k=None, h2: float = 0.0, *, mode: str = "cg",
-          precond: str = "jacobi", precond_prec: str = "fp64", cheb_order: int = 3,
+          precond: str = "jacobi", precond_prec: str | None = None, cheb_order: int = 3,
           lmax: float = 0.0, rtol: float = 1e-10, max_iter: int = 10000,
           fixed_iters: bool = False, inner_rtol: float = 1e-5, max_outer: int = 30,
           check_every: int = 0, profile: bool = False, history: bool = False,
@@ -215,6 +274,10 @@ def solve(mesh: Mesh, b, x0=None, k=None, h2: float = 0.0, *, mode: str = "cg",
             x.zero_()
         else:
             x.copy_(x0)
+    if precond_prec is None:  # the multigrid cycle and the inner solve of refinement: FP32
+        precond_prec = "fp32" if (precond == "pmg" or mode == "mixed_ir") else "fp64"
+    if precond == "pmg" and not mesh._pmg:
+        mesh.setup_pmg()
     opts = L.SolveOpts()
     mesh._lib.sem_solve_opts_default(ctypes.byref(opts))
     opts.mode = L.MODE[mode]

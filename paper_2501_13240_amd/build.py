@@ -30,7 +30,7 @@ CFLAGS = [
 ]
 
 SOURCES = ["api.cpp", "host_setup.cpp", "kernels_ax.hip", "kernels_setup.hip",
-           "kernels_vec.hip", "solver.hip"]
+           "kernels_vec.hip", "solver.hip", "pmg.hip", "pmg_host.cpp"]
 
 
 def _compile(src: str) -> str:

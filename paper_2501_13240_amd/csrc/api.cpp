@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "pmg.hpp"
 #include "solver.hpp"
 
 namespace sem {
@@ -181,6 +182,52 @@ static sem_status estimate_lmax(const sem_mesh* m, SolveWork& W, const double* k
   return SEM_OK;
 }
 
+// Level operators, Jacobi inverses and Chebyshev bounds of the multigrid
+// hierarchy for one solve (k interpolated to every level), and the cycle's
+// work space in the precision it runs in, allocated here so that no
+// allocation happens inside the iterations (which may be graph-captured).
+// Must run before the caller places its own vectors in the fine work space:
+// the bound estimate uses it.
+static sem_status pmg_prepare(const sem_mesh* m, const double* k, double h2, bool f64,
+                              hipStream_t s) {
+  Pmg& P = *m->pmg;
+  sem_status st;
+  for (size_t l = 0; l < P.lv.size(); ++l) {
+    PmgLevel& L = P.lv[l];
+    const sem_mesh* ml = L.m;
+    SolveWork& Wl = work_of(ml);
+    if ((st = Wl.init(ml, 20))) return st;
+    const double* kl = nullptr;
+    if (k && l == 0) {
+      kl = k;
+    } else if (k) {
+      if ((st = L.k64.ensure((size_t)ml->nL * sizeof(double)))) return st;
+      SEM_HIP(launch_interp<double>(m->E, m->n1, ml->n1, L.Ik64.as<double>(), 0, k, nullptr,
+                                    nullptr, L.k64.as<double>(), nullptr, s));
+      kl = L.k64.as<double>();
+    }
+    if ((st = prepare_dinv(ml, Wl, kl, h2, s))) return st;
+    double est = 0.0;
+    if ((st = estimate_lmax(ml, Wl, kl, h2, 20, &est, s))) return st;
+    L.rho_hat = 1.1 * est;
+    L.op64 = op64_of(ml, kl, h2);
+    if ((st = op32_of(ml, Wl, kl, h2, s, L.op32))) return st;
+    L.dinv64 = Wl.dinv.as<double>();
+    L.dinv32 = Wl.dinv32.as<float>();
+    bool ok = true;
+    for (int v = 0; v < 5; ++v) ok = ok && (f64 ? P.vec<double>(L, v) != nullptr : P.vec<float>(L, v) != nullptr);
+    if (f64)
+      ok = ok && Wl.vec<double>(Wl.wL, ml->nL) && Wl.vec<double>(Wl.cd, ml->n_free) &&
+           Wl.vec<double>(Wl.crk, ml->n_free);
+    else
+      ok = ok && Wl.vec<float>(Wl.wL32, ml->nL) && Wl.vec<float>(Wl.cd32, ml->n_free) &&
+           Wl.vec<float>(Wl.crk32, ml->n_free);
+    if (!ok) return fail(SEM_ENOMEM, "multigrid work space");
+  }
+  SEM_HIP(hipStreamSynchronize(s));
+  return SEM_OK;
+}
+
 static bool prec_ok(sem_prec p) {
   return p == SEM_FP64 || p == SEM_FP32 || p == SEM_BF16_MFMA || p == SEM_FP16_MFMA;
 }
@@ -194,7 +241,10 @@ static sem_status check_mesh(const sem_mesh* m) {
 
 }  // namespace sem
 
-sem_mesh::~sem_mesh() { delete work; }
+sem_mesh::~sem_mesh() {
+  pmg_destroy(pmg);
+  delete work;
+}
 
 using namespace sem;
 
@@ -448,6 +498,129 @@ sem_status sem_cheb_apply(const sem_mesh* m, const double* r, double* z, const d
   return SEM_OK;
 }
 
+void sem_pmg_opts_default(sem_pmg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->smooth_order = 3;
+  o->coarse_iters = 30;
+}
+
+sem_status sem_setup_pmg(sem_mesh* m, const sem_mesh_desc* desc, const sem_pmg_opts* opts_in,
+                         void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!desc || !desc->xyz || !desc->gid) return fail(SEM_EINVAL, "desc, xyz and gid are required");
+  if (desc->N != m->N || desc->E != m->E)
+    return fail(SEM_EINVAL, "the description differs from the one the mesh was set up with");
+  sem_pmg_opts opts;
+  if (opts_in) opts = *opts_in;
+  else sem_pmg_opts_default(&opts);
+  if (opts.smooth_order < 1) return fail(SEM_EINVAL, "smooth_order must be >= 1");
+  if (opts.coarse_iters < 1) return fail(SEM_EINVAL, "coarse_iters must be >= 1");
+  std::vector<int> orders;
+  if (opts.n_levels == 0) {
+    for (int n = m->N; ; n /= 2) {
+      orders.push_back(n);
+      if (n <= 1) break;
+    }
+  } else {
+    if (opts.n_levels < 1 || opts.n_levels > SEM_PMG_MAX_LEVELS)
+      return fail(SEM_EINVAL, "n_levels must be in [0, 8]");
+    for (int l = 0; l < opts.n_levels; ++l) orders.push_back(opts.orders[l]);
+    if (orders[0] != m->N) return fail(SEM_EINVAL, "orders[0] must be the mesh order");
+    for (size_t l = 1; l < orders.size(); ++l)
+      if (!(orders[l] >= 1 && orders[l] < orders[l - 1]))
+        return fail(SEM_EINVAL, "level orders must decrease strictly and stay >= 1");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<Pmg, void (*)(Pmg*)> P(new Pmg(), pmg_destroy);
+  P->smooth_order = opts.smooth_order;
+  P->coarse_iters = opts.coarse_iters;
+  P->lv.resize(orders.size());
+  const int64_t E = m->E;
+  sem_status st;
+  for (size_t l = 0; l < orders.size(); ++l) {
+    PmgLevel& L = P->lv[l];
+    L.N = orders[l];
+    if (l == 0) {
+      L.m = m;
+      continue;
+    }
+    const int Nc = orders[l];
+    const int64_t Pc = (int64_t)(Nc + 1) * (Nc + 1) * (Nc + 1);
+    std::vector<int64_t> gid_c((size_t)(E * Pc));
+    std::vector<uint8_t> dir_c(desc->dirichlet ? (size_t)(E * Pc) : 0);
+    std::vector<double> xyz_c((size_t)(3 * E * Pc));
+    if ((st = host_coarse_mesh(m->N, E, desc->gid, desc->dirichlet, desc->xyz, Nc, gid_c.data(),
+                               desc->dirichlet ? dir_c.data() : nullptr, xyz_c.data())))
+      return st;
+    sem_mesh_desc dc{Nc, E, xyz_c.data(), gid_c.data(), desc->dirichlet ? dir_c.data() : nullptr};
+    sem_mesh* mc = nullptr;
+    if ((st = sem_setup_mesh(&dc, stream, &mc))) return st;
+    L.m = mc;
+    L.owned = true;
+    std::vector<double> Ik((size_t)(Nc + 1) * (m->N + 1));
+    if ((st = host_interp_matrix(m->N, Nc, Ik.data())) || (st = upload(L.Ik64, Ik, s))) return st;
+  }
+  for (size_t l = 0; l + 1 < orders.size(); ++l) {
+    PmgLevel& L = P->lv[l];
+    const int nf = orders[l] + 1, nc = orders[l + 1] + 1;
+    std::vector<double> J((size_t)nf * nc), JT((size_t)nc * nf);
+    if ((st = host_interp_matrix(orders[l + 1], orders[l], J.data()))) return st;
+    for (int i = 0; i < nf; ++i)
+      for (int j = 0; j < nc; ++j) JT[(size_t)j * nf + i] = J[(size_t)i * nc + j];
+    std::vector<float> J32(J.begin(), J.end()), JT32(JT.begin(), JT.end());
+    if ((st = upload(L.J64, J, s)) || (st = upload(L.JT64, JT, s)) || (st = upload(L.J32, J32, s)) ||
+        (st = upload(L.JT32, JT32, s)))
+      return st;
+  }
+  SEM_HIP(hipStreamSynchronize(s));
+  pmg_destroy(m->pmg);
+  m->pmg = P.release();
+  return SEM_OK;
+}
+
+sem_status sem_pmg_info(const sem_mesh* m, int32_t* n_levels, int32_t* orders, double* rho_hat) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!m->pmg) return fail(SEM_EINVAL, "no multigrid hierarchy: call sem_setup_pmg first");
+  const auto& lv = m->pmg->lv;
+  if (n_levels) *n_levels = (int32_t)lv.size();
+  for (size_t l = 0; l < SEM_PMG_MAX_LEVELS; ++l) {
+    if (orders) orders[l] = l < lv.size() ? lv[l].N : 0;
+    if (rho_hat) rho_hat[l] = l < lv.size() ? lv[l].rho_hat : 0.0;
+  }
+  return SEM_OK;
+}
+
+sem_status sem_pmg_apply(const sem_mesh* m, const double* r, double* z, const double* k,
+                         double h2, sem_prec prec, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!r || !z) return fail(SEM_EINVAL, "r and z must not be NULL");
+  if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_EINVAL, "prec must be FP64 or FP32");
+  if (!m->pmg) return fail(SEM_EINVAL, "no multigrid hierarchy: call sem_setup_pmg first");
+  hipStream_t s = (hipStream_t)stream;
+  sem_status st;
+  if ((st = pmg_prepare(m, k, h2, prec == SEM_FP64, s))) return st;
+  SolveWork& W = work_of(m);
+  double* rf = W.vec<double>(W.tmpf, m->n_free);
+  double* zf = W.vec<double>(W.z, m->n_free);
+  if (!rf || !zf) return fail(SEM_ENOMEM, "work space");
+  SEM_HIP((launch_local_to_free_avg<double, double>(m, r, rf, s)));
+  if (prec == SEM_FP64) st = pmg_precond<double, double>(m, W, rf, zf, ChebCg(), s, nullptr);
+  else st = pmg_precond<double, float>(m, W, rf, zf, ChebCg(), s, nullptr);
+  if (st) return st;
+  SEM_HIP((launch_free_to_local<double, double>(m, zf, z, s)));
+  return SEM_OK;
+}
+
+sem_status sem_host_coarse_mesh(int32_t N, int64_t E, const int64_t* gid,
+                                const uint8_t* dirichlet, const double* xyz, int32_t Nc,
+                                int64_t* gid_c, uint8_t* dirichlet_c, double* xyz_c) {
+  if ((xyz == nullptr) != (xyz_c == nullptr))
+    return fail(SEM_EINVAL, "xyz and xyz_c must both be given or both be NULL");
+  return host_coarse_mesh(N, E, gid, dirichlet, xyz, Nc, gid_c, dirichlet_c, xyz_c);
+}
+
 sem_status sem_lmax_estimate(const sem_mesh* m, const double* k, double h2, int32_t steps,
                              double* lmax, void* stream) {
   if (sem_status st = check_mesh(m)) return st;
@@ -468,8 +641,14 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
   else sem_solve_opts_default(&opts);
   if (opts.mode != SEM_SOLVE_CG && opts.mode != SEM_SOLVE_MIXED_IR)
     return fail(SEM_EINVAL, "unknown solve mode");
-  if (opts.precond != SEM_PRECOND_JACOBI && opts.precond != SEM_PRECOND_CHEBYSHEV)
+  if (opts.precond != SEM_PRECOND_JACOBI && opts.precond != SEM_PRECOND_CHEBYSHEV &&
+      opts.precond != SEM_PRECOND_PMG)
     return fail(SEM_EINVAL, "unknown preconditioner");
+  const bool pmg = opts.precond == SEM_PRECOND_PMG;
+  if (pmg && !m->pmg) return fail(SEM_EINVAL, "multigrid preconditioner: call sem_setup_pmg first");
+  if (pmg && opts.precond_prec != SEM_FP32 &&
+      !(opts.precond_prec == SEM_FP64 && opts.mode == SEM_SOLVE_CG))
+    return fail(SEM_EINVAL, "the multigrid cycle runs in SEM_FP32 (or SEM_FP64 in mode CG)");
   if (opts.cheb_order < 1) return fail(SEM_EINVAL, "cheb_order must be >= 1");
   if (opts.max_iter < 0) return fail(SEM_EINVAL, "max_iter must be >= 0");
   if (!(opts.rtol >= 0.0)) return fail(SEM_EINVAL, "rtol must be >= 0");
@@ -501,7 +680,9 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
 
   const bool neumann = m->nullspace && h2 == 0.0;
   const bool cheb = opts.precond == SEM_PRECOND_CHEBYSHEV;
-  double lmax = opts.lmax;
+  const bool pmg64 = pmg && opts.precond_prec == SEM_FP64;
+  if (pmg && (st = pmg_prepare(m, k, h2, pmg64, s))) return st;
+  double lmax = pmg ? m->pmg->lv[0].rho_hat : opts.lmax;
   if (cheb && !(lmax > 0.0)) {
     double est = 0.0;
     if ((st = estimate_lmax(m, W, k, h2, 20, &est, s))) return st;
@@ -548,7 +729,18 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     a.dinv = dinv;
     a.precond = opts.precond;
     a.cheb_order = opts.cheb_order;
-    if (cheb) {
+    if (pmg) {
+      if (pmg64)
+        a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
+                    const ChebCg& cg, hipStream_t ss, int* ap) {
+          return pmg_precond<double, double>(mm, WW, r, z, cg, ss, ap);
+        };
+      else
+        a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
+                    const ChebCg& cg, hipStream_t ss, int* ap) {
+          return pmg_precond<double, float>(mm, WW, r, z, cg, ss, ap);
+        };
+    } else if (cheb) {
       const int order = opts.cheb_order;
       if (opts.precond_prec == SEM_FP64) {
         a.cheb = [op64, dinv, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
@@ -595,7 +787,12 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     a.dinv = dinv32;
     a.precond = opts.precond;
     a.cheb_order = opts.cheb_order;
-    if (cheb) {
+    if (pmg) {
+      a.cheb = [](const sem_mesh* mm, SolveWork& WW, const float* rr, float* z, const ChebCg& cg,
+                  hipStream_t ss, int* ap) {
+        return pmg_precond<float, float>(mm, WW, rr, z, cg, ss, ap);
+      };
+    } else if (cheb) {
       const int order = opts.cheb_order;
       a.cheb = [opc, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const float* rr,
                                           float* z, const ChebCg& cg, hipStream_t ss, int* ap) {
@@ -669,7 +866,7 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     stats->converged = converged ? 1 : 0;
     stats->rel_res = rel;
     stats->time_ms = ms;
-    stats->lmax = cheb ? lmax : 0.0;
+    stats->lmax = (cheb || pmg) ? lmax : 0.0;
     double ax_ms = 0.0;
     for (int i = 0; i + 1 < W.ev_used; i += 2) {
       float d = 0.f;

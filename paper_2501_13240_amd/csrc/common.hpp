@@ -41,6 +41,20 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevBuf() { release(); }
   void release() {
     if (p) (void)hipFree(p);
@@ -141,6 +155,7 @@ __device__ __forceinline__ Tacc segment_sum(const int32_t* __restrict__ perm,
 
 // ------------------------------------------------------------- the mesh
 struct SolveWork;
+struct Pmg;
 
 }  // namespace sem
 
@@ -161,6 +176,7 @@ struct sem_mesh {
   double cached_lmax_h2 = -1.0;
   double cached_lmax = 0.0;
   sem::SolveWork* work = nullptr;
+  sem::Pmg* pmg = nullptr;              // p-multigrid hierarchy (sem_setup_pmg)
   ~sem_mesh();
 };
 

@@ -398,6 +398,124 @@ __global__ __launch_bounds__(kVecBlock) void k_cheb_step(
   if constexpr (DOTS) block_partials<2>(v, part);
 }
 
+// ------------------------------------------- fixed-count CG on the device
+//
+// The coarsest level of the multigrid cycle runs a fixed number of Jacobi-PCG
+// iterations from zero with no host read-back: the initial scalars are formed
+// on the device and the usual iteration kernels follow.  Every kernel returns
+// at once when the enclosing solve (`outer`) has finished.
+
+// partials of sum(b) (mean of a singular problem's right-hand side)
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_fcg_sum(int64_t nf, const T* __restrict__ b,
+                                                       double* __restrict__ part,
+                                                       const CgScalars* __restrict__ outer) {
+  if (outer && outer->done) return;
+  double v[1] = {0.0};
+  BLOCK_CHUNK(g, nf) v[0] += (double)b[g];
+  block_partials<1>(v, part);
+}
+
+// x = 0; r = b (minus its mean when singular); p = S r; partials of r.p
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_fcg_init(
+    int64_t nf, const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
+    const T* __restrict__ dinv, const double* __restrict__ part_in, int nblk, int neumann,
+    double inv_n, double* __restrict__ part, const CgScalars* __restrict__ outer) {
+  if (outer && outer->done) return;
+  double mean = 0.0;
+  if (neumann) {
+    double S[1];
+    block_total<1>(part_in, nblk, S);
+    mean = S[0] * inv_n;
+  }
+  const T mt = (T)mean;
+  double v[1] = {0.0};
+  BLOCK_CHUNK(g, nf) {
+    const T rg = b[g] - mt;
+    const T pg = dinv[g] * rg;
+    x[g] = T(0);
+    r[g] = rg;
+    p[g] = pg;
+    v[0] += (double)rg * (double)pg;
+  }
+  block_partials<1>(v, part);
+}
+
+// one block: the solve's scalars from the r.p partials (done at once when the
+// enclosing solve has finished or the right-hand side vanishes)
+__global__ __launch_bounds__(kVecBlock) void k_fcg_scalars(const double* __restrict__ part,
+                                                           int nblk, CgScalars* __restrict__ sc,
+                                                           int iters, int neumann, double inv_n,
+                                                           const CgScalars* __restrict__ outer) {
+  double S[1];
+  block_total<1>(part, nblk, S);
+  if (threadIdx.x == 0) {
+    const double rho = S[0];
+    const bool stop = (outer && outer->done) || !(rho > 0.0) || !finite(rho) || iters <= 0;
+    sc->rho = rho;
+    sc->alpha = 0.0;
+    sc->beta = 0.0;
+    sc->bb = 0.0;
+    sc->tol2 = 0.0;
+    sc->rr = 0.0;
+    sc->mean_w = 0.0;
+    sc->inv_n = inv_n;
+    sc->zw = 0.0;
+    sc->it = 0;
+    sc->done = stop ? 1 : 0;
+    sc->status = 0;
+    sc->max_it = iters;
+    sc->fixed = 1;
+    sc->neumann = neumann;
+    sc->flexible = 0;
+    sc->kcur = 0;
+    sc->rho2[0] = rho;
+    sc->rho2[1] = 0.0;
+  }
+}
+
+// convergence decision of a flexible CG iteration whose preconditioner does
+// not take it itself (one block; the update wrote two partials per block)
+__global__ __launch_bounds__(kVecBlock) void k_gate(const double* __restrict__ check_in, int nblk,
+                                                    CgScalars* __restrict__ sc,
+                                                    double* __restrict__ hist) {
+  if (sc->done) return;
+  const int kit = sc->kcur;
+  double S[2];
+  block_total<2>(check_in, nblk, S);
+  (void)cg_check(S[0], kit, sc, hist);
+}
+
+// z = x (to the CG's type); with a solve: partials of z.r and z.(w - mean_w)
+template <typename Tr, typename Tp>
+__global__ __launch_bounds__(kVecBlock) void k_flex_dots(int64_t nf, const Tp* __restrict__ x,
+                                                         Tr* __restrict__ z,
+                                                         const Tr* __restrict__ r,
+                                                         const Tr* __restrict__ w,
+                                                         double* __restrict__ part,
+                                                         const CgScalars* __restrict__ sc) {
+  if (sc && sc->done) return;
+  const double mw = sc ? sc->mean_w : 0.0;
+  double v[2] = {0.0, 0.0};
+  BLOCK_CHUNK(g, nf) {
+    const Tr zg = (Tr)x[g];
+    z[g] = zg;
+    if (sc) {
+      v[0] += (double)zg * (double)r[g];
+      v[1] += (double)zg * ((double)w[g] - mw);
+    }
+  }
+  if (sc) block_partials<2>(v, part);
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert_skip(int64_t n, const Tin* __restrict__ a, Tout* __restrict__ b,
+                               const CgScalars* __restrict__ sc) {
+  if (sc && sc->done) return;
+  GRID_STRIDE(g, n) b[g] = (Tout)a[g];
+}
+
 inline unsigned vgrid(int64_t n) {
   int64_t b = (n + kVecBlock - 1) / kVecBlock;
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, kReduceBlocks));
@@ -518,6 +636,8 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
   const double c0 = 4.0 / (3.0 * lmax);
   Op<Tp> opk = op;
   if (flex) opk.skip = &cg.sc->done;
+  else if (cg.skip_sc) opk.skip = &cg.skip_sc->done;
+  CgScalars* skip_sc = const_cast<CgScalars*>(cg.skip_sc);
   if (flex && order == 1)
     hipLaunchKernelGGL((k_cheb_init<Tr, Tp, true, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, r,
                        dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.part_out, cg.sc,
@@ -528,8 +648,8 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
                        cg.hist);
   else
     hipLaunchKernelGGL((k_cheb_init<Tr, Tp, false, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, r,
-                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.part_out,
-                       (CgScalars*)nullptr, cg.hist);
+                       dinv, d, rk, z, c0, wcg, cg.check_in, cg.nblk, cg.part_out, skip_sc,
+                       cg.hist);
   SEM_CHECK_LAUNCH("Chebyshev init");
   for (int k = 1; k < order; ++k) {
     sem_status st = apply_op<Tp>(m, W, opk, d, wL, s, false);
@@ -544,7 +664,7 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
     else
       hipLaunchKernelGGL((k_cheb_step<Tp, Tr, false>), dim3(nb), dim3(kVecBlock), 0, s, nf,
                          m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
-                         r, wcg, cg.part_out, cg.sc);
+                         r, wcg, cg.part_out, flex ? cg.sc : cg.skip_sc);
     SEM_CHECK_LAUNCH("Chebyshev step");
   }
   return SEM_OK;
@@ -836,5 +956,91 @@ sem_status ir_update(const sem_mesh* m, double* x, const float* e, double sc, hi
   SEM_CHECK_LAUNCH("refinement update");
   return SEM_OK;
 }
+
+// ------------------------------------------------ multigrid coarse-level pieces
+
+unsigned vec_grid(int64_t n) { return vgrid(n); }
+
+template <typename T>
+sem_status cg_fixed_device(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* dinv,
+                           const T* b, T* x, T* r, T* p, T* w, T* wL, int iters, bool neumann,
+                           const CgScalars* outer, hipStream_t s) {
+  const int64_t nf = m->n_free;
+  const unsigned nb = vgrid(nf);
+  double* partA = W.part.as<double>();
+  double* partB = partA + kReduceBlocks * kMaxReduce;
+  CgScalars* sc = W.sc.as<CgScalars>();
+  if (!partA || !sc) return fail(SEM_EINVAL, "coarse solve work space not initialised");
+  const double inv_n = 1.0 / (double)std::max<int64_t>(nf, 1);
+  if (neumann)
+    hipLaunchKernelGGL((k_fcg_sum<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, b, partA, outer);
+  hipLaunchKernelGGL((k_fcg_init<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, b, x, r, p, dinv, partA,
+                     (int)nb, neumann ? 1 : 0, inv_n, partB, outer);
+  hipLaunchKernelGGL(k_fcg_scalars, dim3(1), dim3(kVecBlock), 0, s, partB, (int)nb, sc, iters,
+                     neumann ? 1 : 0, inv_n, outer);
+  SEM_CHECK_LAUNCH("coarse CG start");
+  Op<T> opi = op;
+  opi.skip = &sc->done;
+  for (int it = 0; it < iters; ++it) {
+    sem_status st = apply_op<T>(m, W, opi, p, wL, s, false);
+    if (st) return st;
+    hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
+                       m->fperm.as<int32_t>(), wL, p, w, partA, sc);
+    hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w, dinv,
+                       partA, (int)nb, partB, sc, (double*)nullptr);
+    hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, dinv, partB,
+                       (int)nb, sc, (double*)nullptr, (double*)nullptr);
+  }
+  SEM_CHECK_LAUNCH("coarse CG");
+  return SEM_OK;
+}
+template sem_status cg_fixed_device<double>(const sem_mesh*, SolveWork&, const Op<double>&,
+                                            const double*, const double*, double*, double*,
+                                            double*, double*, double*, int, bool,
+                                            const CgScalars*, hipStream_t);
+template sem_status cg_fixed_device<float>(const sem_mesh*, SolveWork&, const Op<float>&,
+                                           const float*, const float*, float*, float*, float*,
+                                           float*, float*, int, bool, const CgScalars*,
+                                           hipStream_t);
+
+sem_status launch_cg_gate(const double* check_in, int nblk, CgScalars* sc, double* hist,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_gate, dim3(1), dim3(kVecBlock), 0, s, check_in, nblk, sc, hist);
+  SEM_CHECK_LAUNCH("convergence gate");
+  return SEM_OK;
+}
+
+template <typename Tr, typename Tp>
+sem_status launch_flex_dots(int64_t nf, const Tp* x, Tr* z, const Tr* r, const Tr* w,
+                            double* part, const CgScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL((k_flex_dots<Tr, Tp>), dim3(vgrid(nf)), dim3(kVecBlock), 0, s, nf, x, z, r,
+                     w, part, sc);
+  SEM_CHECK_LAUNCH("preconditioner output");
+  return SEM_OK;
+}
+template sem_status launch_flex_dots<double, double>(int64_t, const double*, double*,
+                                                     const double*, const double*, double*,
+                                                     const CgScalars*, hipStream_t);
+template sem_status launch_flex_dots<double, float>(int64_t, const float*, double*, const double*,
+                                                    const double*, double*, const CgScalars*,
+                                                    hipStream_t);
+template sem_status launch_flex_dots<float, float>(int64_t, const float*, float*, const float*,
+                                                   const float*, double*, const CgScalars*,
+                                                   hipStream_t);
+
+template <typename Tin, typename Tout>
+sem_status launch_convert_skip(int64_t n, const Tin* a, Tout* b, const CgScalars* sc,
+                               hipStream_t s) {
+  hipLaunchKernelGGL((k_convert_skip<Tin, Tout>), dim3(vgrid(n)), dim3(kVecBlock), 0, s, n, a, b,
+                     sc);
+  SEM_CHECK_LAUNCH("convert");
+  return SEM_OK;
+}
+template sem_status launch_convert_skip<double, float>(int64_t, const double*, float*,
+                                                       const CgScalars*, hipStream_t);
+template sem_status launch_convert_skip<double, double>(int64_t, const double*, double*,
+                                                        const CgScalars*, hipStream_t);
+template sem_status launch_convert_skip<float, float>(int64_t, const float*, float*,
+                                                      const CgScalars*, hipStream_t);
 
 }  // namespace sem

@@ -57,6 +57,9 @@ struct ChebCg {
   int nblk = 0;
   double* part_out = nullptr;
   double* hist = nullptr;
+  // without `sc`: a solve's scalars whose `done` flag makes the pass return at
+  // once (a preconditioner pass inside a V-cycle of a flexible CG)
+  const CgScalars* skip_sc = nullptr;
 };
 
 template <typename T>
@@ -105,5 +108,27 @@ sem_status ir_residual(const sem_mesh* m, SolveWork& W, const Op<double>& op, co
 sem_status ir_prepare(const sem_mesh* m, const double* r, float* r32, double shift, double scale,
                       hipStream_t s);
 sem_status ir_update(const sem_mesh* m, double* x, const float* e, double sc, hipStream_t s);
+
+// grid of the reducing vector kernels for n elements (= number of partials)
+unsigned vec_grid(int64_t n);
+
+// `iters` Jacobi-PCG iterations from x = 0 entirely on the device (W.sc holds
+// the scalars; r, p, w free scratch, wL local scratch); the constant mode is
+// projected out when `neumann`.  Every launch returns at once when `outer`
+// (nullable) has finished.
+template <typename T>
+sem_status cg_fixed_device(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* dinv,
+                           const T* b, T* x, T* r, T* p, T* w, T* wL, int iters, bool neumann,
+                           const CgScalars* outer, hipStream_t s);
+// convergence decision of a flexible CG iteration from the update's r.r partials
+sem_status launch_cg_gate(const double* check_in, int nblk, CgScalars* sc, double* hist,
+                          hipStream_t s);
+// z = x in the CG's type; with sc: partials of z.r and z.(w - mean_w) into part
+template <typename Tr, typename Tp>
+sem_status launch_flex_dots(int64_t nf, const Tp* x, Tr* z, const Tr* r, const Tr* w,
+                            double* part, const CgScalars* sc, hipStream_t s);
+template <typename Tin, typename Tout>
+sem_status launch_convert_skip(int64_t n, const Tin* a, Tout* b, const CgScalars* sc,
+                               hipStream_t s);
 
 }  // namespace sem

@@ -41,6 +41,38 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.SolveOpts) == 72
     assert ctypes.sizeof(L.SolveStats) == 56
     assert ctypes.sizeof(L.MeshInfo) == 48
+    assert ctypes.sizeof(L.PmgOpts) == 44
+
+
+_STRUCTS = {"sem_mesh_desc": L.MeshDesc, "sem_mesh_info": L.MeshInfo,
+            "sem_solve_opts": L.SolveOpts, "sem_solve_stats": L.SolveStats,
+            "sem_pmg_opts": L.PmgOpts}
+
+
+def test_struct_layouts_match_a_c_compiler(tmp_path):
+    """sizeof/offsetof of every public struct as gcc lays it out from the
+    header, against the binding's ctypes declarations."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "sem.h"', "int main(void) {"]
+    for cname, py in _STRUCTS.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for cname, py in _STRUCTS.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 CLOSED = {
@@ -160,3 +192,41 @@ def test_null_handles_are_rejected():
     opts = L.SolveOpts()
     lib.sem_solve_opts_default(ctypes.byref(opts))
     assert opts.rtol == 1e-10 and opts.cheb_order == 3 and opts.max_iter == 10000
+
+
+def _same_partition(a, b):
+    a, b = a.ravel(), b.ravel()
+    pairs = np.unique(np.stack([a, b], 1), axis=0)
+    return len(pairs) == len(np.unique(a)) == len(np.unique(b))
+
+
+@pytest.mark.parametrize("N,Nc", [(7, 3), (3, 1), (9, 4), (4, 2)])
+@pytest.mark.parametrize("kw", [
+    dict(periodic=(False, False, False), dirichlet="all", jitter=0.05),
+    dict(periodic=(True, True, False), dirichlet="z", z_ratio=4.0,
+         deform=dict(a=0.15, seed=1, kind="periodic")),
+    dict(periodic=(False, True, True), dirichlet="none", jitter=0.05),
+])
+def test_host_coarse_mesh_matches_oracle(N, Nc, kw):
+    """The library's coarse-order mesh (multigrid levels) against the oracle's:
+    coordinates, the partition of local points into unknowns, Dirichlet flags."""
+    import oracle
+    m = box_mesh(N, (3, 3, 4), (1.0, 1.2, 0.9), **kw)
+    xo, go, do = oracle.coarse_mesh(m.xyz, m.gid, m.dirichlet, N, Nc)
+    xc, gc, dc = sem.host_coarse_mesh(N, m.gid, m.dirichlet, m.xyz, Nc)
+    np.testing.assert_allclose(xc, xo, atol=1e-13)
+    assert _same_partition(gc, go)
+    if do is None:
+        assert dc is None
+    else:
+        np.testing.assert_array_equal(dc, do)
+
+
+def test_host_coarse_mesh_rejects_bad_input():
+    m = box_mesh(3, (2, 2, 2), dirichlet="all")
+    with pytest.raises(sem.SemError, match="EINVAL"):
+        sem.host_coarse_mesh(3, m.gid, m.dirichlet, m.xyz, 3)
+    # one element across a periodic direction: a face's corners share ids
+    p = box_mesh(4, (1, 2, 2), periodic=(True, False, False), dirichlet="none")
+    with pytest.raises(sem.SemError, match="share a global id"):
+        sem.host_coarse_mesh(4, p.gid, None, p.xyz, 2)
