@@ -134,11 +134,16 @@ def mixed_vs_fp64(sem):
         "fp64_cg_fp32_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="fp32"),
         "fp64_cg_bf16_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="bf16_mfma"),
         "mixed_ir_fp32_cg": dict(mode="mixed_ir", precond="jacobi", precond_prec="fp32"),
+        "fp64_pmg_fcg": dict(mode="cg", precond="pmg", precond_prec="fp64"),
+        "fp64_cg_fp32_pmg": dict(mode="cg", precond="pmg", precond_prec="fp32"),
+        "mixed_ir_fp32_pmg": dict(mode="mixed_ir", precond="pmg", precond_prec="fp32"),
     }
     out = {"workload": "32x32x32 hexahedra, N=9, tanh 1:20 z-clustering, seeded wall-preserving "
                        "deformation, all-Neumann (constant mode removed), zero-mean random rhs",
            "n_unique": M.info["n_unique"], "rtol": 1e-10}
     sem.lmax_estimate(M)  # bound estimate shared by the Chebyshev variants (cached)
+    M.setup_pmg()
+    sem.solve(M, b, rtol=1e-10, max_iter=2, precond="pmg", raise_on_noconv=False)  # level bounds
     for name, v in variants.items():
         x, st = sem.solve(M, b, rtol=1e-10, max_iter=30000, **v)
         res = true_rel_residual(sem, M, b, x)
@@ -151,7 +156,32 @@ def mixed_vs_fp64(sem):
     out["fastest_mixed"] = best
     if best:
         out["speedup_vs_fp64"] = out["fp64_jacobi_cg"]["ms"] / out[best]["ms"]
+    # the same preconditioner in FP64 and with the FP32 cycle
+    out["pmg_fp32_cycle_speedup_vs_fp64_pmg"] = (out["fp64_pmg_fcg"]["ms"]
+                                                 / out["fp64_cg_fp32_pmg"]["ms"])
     M.close()
+    return out
+
+
+def to_tolerance(sem, M, b):
+    """Time to ||b - A x|| <= 1e-10 ||b|| on the benchmark mesh: FP64 Jacobi
+    CG against p-multigrid-preconditioned flexible CG (FP64 and FP32 cycles)
+    and refinement around it."""
+    variants = {
+        "fp64_jacobi_cg": dict(mode="cg", precond="jacobi"),
+        "fp64_pmg_fcg": dict(mode="cg", precond="pmg", precond_prec="fp64"),
+        "fp64_cg_fp32_pmg": dict(mode="cg", precond="pmg", precond_prec="fp32"),
+        "mixed_ir_fp32_pmg": dict(mode="mixed_ir", precond="pmg", precond_prec="fp32"),
+    }
+    M.setup_pmg()
+    sem.solve(M, b, rtol=1e-10, max_iter=2, precond="pmg", raise_on_noconv=False)  # level bounds
+    out = {"rtol": 1e-10}
+    for name, v in variants.items():
+        x, st = sem.solve(M, b, rtol=1e-10, max_iter=30000, **v)
+        out[name] = {"ms": st["time_ms"], "iters": st["iters"], "outer": st["outer_iters"],
+                     "true_rel_res": true_rel_residual(sem, M, b, x)}
+        log(f"  {name}: {st['time_ms']:.1f} ms, {st['iters']} it, "
+            f"true rel res {out[name]['true_rel_res']:.2e}")
     return out
 
 
@@ -194,6 +224,8 @@ def small_solves(sem):
         "fp64_cg_fp16_cheb3": dict(mode="cg", precond="chebyshev", precond_prec="fp16_mfma"),
         "mixed_ir_fp32_cg": dict(mode="mixed_ir", precond="jacobi", precond_prec="fp32"),
         "mixed_ir_fp32_cheb3": dict(mode="mixed_ir", precond="chebyshev", precond_prec="fp32"),
+        "fp64_pmg_fcg": dict(mode="cg", precond="pmg", precond_prec="fp64"),
+        "fp64_cg_fp32_pmg": dict(mode="cg", precond="pmg", precond_prec="fp32"),
     }
     out = {}
     for N in (7, 9):
@@ -362,6 +394,8 @@ def main():
         "gs": gs,
     }
     if not args.no_extras:
+        log("to 1e-10 on the benchmark mesh ...")
+        out["to_tolerance"] = to_tolerance(sem, M, b)
         M.close()
         log("small solves (4^3 unit cube, N = 7 and 9) ...")
         out["small_solves"] = small_solves(sem)

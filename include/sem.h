@@ -258,7 +258,8 @@ typedef struct {
   int32_t coarse_iters;                /* Jacobi-PCG iterations on the coarsest level, >= 1 */
 } sem_pmg_opts;
 
-/* Defaults: n_levels 0, smooth_order 3, coarse_iters 30. */
+/* Defaults: n_levels 0, smooth_order 5, coarse_iters 20 (the fastest of the
+ * settings measured on the benchmark meshes to a 1e-10 residual). */
 void sem_pmg_opts_default(sem_pmg_opts* opts);
 
 /* Build (or rebuild) the hierarchy of `mesh` from the description it was set

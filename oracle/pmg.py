@@ -185,8 +185,8 @@ def fixed_pcg(A, b, dinv, iters, project=None):
 class PMG:
     """The level hierarchy and the V-cycle (FP64)."""
 
-    def __init__(self, xyz, gid, dirichlet, N, k=None, h2=0.0, orders=None, smooth_order=3,
-                 coarse_iters=30, coarse="cg", rho=None):
+    def __init__(self, xyz, gid, dirichlet, N, k=None, h2=0.0, orders=None, smooth_order=5,
+                 coarse_iters=20, coarse="cg", rho=None):
         self.orders = level_orders(N) if orders is None else list(orders)
         self.m = smooth_order
         self.coarse_iters = coarse_iters

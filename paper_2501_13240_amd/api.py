@@ -95,7 +95,7 @@ class Mesh:
     def handle(self):
         return self._h
 
-    def setup_pmg(self, orders=None, smooth_order: int = 3, coarse_iters: int = 30):
+    def setup_pmg(self, orders=None, smooth_order: int = 5, coarse_iters: int = 20):
         """Build the p-multigrid hierarchy (sem_setup_pmg); orders default to
         N, N//2, ..., 1."""
         opts = L.PmgOpts()
