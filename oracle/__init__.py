@@ -34,7 +34,7 @@ from .geometry import geometric_factors
 from .operator import (local_apply, local_diagonal, mass_apply, kgrad_contraction,
                        local_apply_lowprec, local_apply_majorant, round_to_format, block_scale)
 from .assembly import Numbering, explicit_matrix, element_matrices
-from .solvers import Problem, pcg, chebyshev_apply, lanczos_lmax
+from .solvers import Problem, pcg, chebyshev_apply, chebyshev1_apply, lanczos_lmax
 from .pmg import PMG, coarse_mesh, interpolation_matrix, level_orders
 from .grad import solve_and_adjoint_gradient
 
@@ -58,6 +58,7 @@ __all__ = [
     "Problem",
     "pcg",
     "chebyshev_apply",
+    "chebyshev1_apply",
     "lanczos_lmax",
     "solve_and_adjoint_gradient",
     "PMG",

@@ -83,6 +83,12 @@ class Problem:
                 rho_hat = 1.1 * lanczos_lmax(self.apply, dinv, rng.standard_normal(b.size), 20, proj)
             M = lambda r: chebyshev_apply(self.apply, dinv, r, m, rho_hat)
             flexible = True
+        elif precond == "chebyshev1":
+            if rho_hat is None:
+                rng = np.random.default_rng(7)
+                rho_hat = 1.1 * lanczos_lmax(self.apply, dinv, rng.standard_normal(b.size), 20, proj)
+            M = lambda r: chebyshev1_apply(self.apply, dinv, r, m, rho_hat)
+            flexible = True
         else:
             raise ValueError(precond)
         res = pcg(self.apply, b, M, rtol=rtol, max_iter=max_iter, x0=x0,
@@ -149,6 +155,35 @@ def chebyshev_apply(A, dinv, r, m, rho_hat):
         x = x + d
         rk = rk - A(d)
         d = ((2 * k - 1) / (2 * k + 3)) * d + ((8 * k + 4) / ((2 * k + 3) * rho_hat)) * (dinv * rk)
+    return x + d
+
+
+def chebyshev1_apply(A, dinv, r, m, rho_hat, ratio=10.0):
+    """z = p_m(S A) S r, the classical (first-kind) Chebyshev semi-iteration
+    of order m (m-1 operator applies) from zero on the interval
+    [rho_hat / ratio, rho_hat]: with theta the interval's centre, delta its
+    half width and sigma = theta / delta, the iterates follow the three-term
+    recurrence of the scaled first-kind polynomials,
+        d_0 = S r / theta,  x_1 = d_0,
+        rho_0 = 1 / sigma,  rho_k = 1 / (2 sigma - rho_{k-1}),
+        r_k = r_{k-1} - A d_{k-1},
+        d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) S r_k,
+        x_{k+1} = x_k + d_k,
+    so that the error polynomial is 1 - lambda p(lambda) =
+    T_m((theta - lambda) / delta) / T_m(sigma)."""
+    lo, hi = rho_hat / ratio, rho_hat
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    rho_prev = 1.0 / sigma
+    d = (dinv * r) / theta
+    x = np.zeros_like(r)
+    rk = r.copy()
+    for _ in range(1, m):
+        x = x + d
+        rk = rk - A(d)
+        rho = 1.0 / (2.0 * sigma - rho_prev)
+        d = rho * rho_prev * d + (2.0 * rho / delta) * (dinv * rk)
+        rho_prev = rho
     return x + d
 
 

@@ -167,6 +167,34 @@ def test_chebyshev_error_polynomial_closed_form(m):
     assert abs(abs(e[-1]) - 1.0 / (2 * m + 1)) < 1e-13
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 8])
+def test_first_kind_chebyshev_error_polynomial_closed_form(m):
+    """Classical semi-iteration on [rho/10, rho]: 1 - lam p(lam) equals
+    T_m((theta - lam)/delta) / T_m(theta/delta) (numpy's Chebyshev series)."""
+    from numpy.polynomial import chebyshev as C
+    rho_hat = 1.7
+    lo, hi = rho_hat / 10, rho_hat
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    lam = np.linspace(1e-4, rho_hat, 301)
+    z = oracle.chebyshev1_apply(lambda v: lam * v, np.ones_like(lam), np.ones_like(lam), m, rho_hat)
+    Tm = np.zeros(m + 1)
+    Tm[m] = 1.0
+    expect = C.chebval((theta - lam) / delta, Tm) / C.chebval(theta / delta, Tm)
+    np.testing.assert_allclose(1.0 - lam * z, expect, atol=1e-12)
+    inside = lam >= lo
+    assert np.all(np.abs(1.0 - lam[inside] * z[inside]) <= 1.0 / C.chebval(theta / delta, Tm) + 1e-12)
+
+
+def test_first_kind_chebyshev_pcg_converges_to_the_jacobi_solution():
+    N = 3
+    m, P = _small_problem(N, k=True, h2=0.2)
+    b = np.random.default_rng(8).standard_normal(P.num.n_free)
+    ref = P.solve(b, rtol=1e-12)
+    res = P.solve(b, rtol=1e-10, precond="chebyshev1", m=4)
+    assert res["converged"] and res["iters"] < ref["iters"]
+    assert np.linalg.norm(res["x"] - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+
+
 def test_chebyshev_symmetric_and_contracting_on_operator():
     N = 3
     m, P = _small_problem(N, k=True, h2=0.2)
