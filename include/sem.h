@@ -92,13 +92,19 @@ typedef struct {
   int32_t has_nullspace; /* 1 if no Dirichlet node: the constant is in the kernel for h2 = 0 */
 } sem_mesh_info;
 
-/* Preconditioner of the CG.  SEM_PRECOND_PMG: one p-multigrid V-cycle per
- * iteration (Sec. 2.2: the default pressure preconditioner, p-multigrid with
- * fourth-kind Chebyshev-accelerated smoothing); needs sem_setup_pmg first. */
+/* Preconditioner of the CG.  SEM_PRECOND_CHEBYSHEV: fourth-kind Chebyshev-
+ * Jacobi of order cheb_order (the acceleration Sec. 2.2 names).
+ * SEM_PRECOND_PMG: one p-multigrid V-cycle per iteration (Sec. 2.2: the
+ * default pressure preconditioner, p-multigrid with fourth-kind Chebyshev-
+ * accelerated smoothing); needs sem_setup_pmg first.
+ * SEM_PRECOND_CHEBYSHEV_FIRST: the classical first-kind Chebyshev semi-
+ * iteration of order cheb_order on [rho_hat/10, rho_hat] (a comparison
+ * variant; same cost per call as the fourth kind). */
 typedef enum {
   SEM_PRECOND_JACOBI = 0,
   SEM_PRECOND_CHEBYSHEV = 1,
-  SEM_PRECOND_PMG = 2
+  SEM_PRECOND_PMG = 2,
+  SEM_PRECOND_CHEBYSHEV_FIRST = 3
 } sem_precond;
 typedef enum { SEM_SOLVE_CG = 0, SEM_SOLVE_MIXED_IR = 1 } sem_solve_mode;
 

@@ -23,7 +23,7 @@ SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EDEVICE, SEM_ENOCONV, SEM_EBREAKDOWN, SEM_EN
 STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_ENOMEM", -3: "SEM_EDEVICE",
                 -4: "SEM_ENOCONV", -5: "SEM_EBREAKDOWN", -6: "SEM_ENOTSUP"}
 PREC = {"fp64": 0, "fp32": 1, "bf16_mfma": 2, "fp16_mfma": 3}
-PRECOND = {"jacobi": 0, "chebyshev": 1, "pmg": 2}
+PRECOND = {"jacobi": 0, "chebyshev": 1, "pmg": 2, "chebyshev1": 3}
 PMG_MAX_LEVELS = 8
 MODE = {"cg": 0, "mixed_ir": 1}
 

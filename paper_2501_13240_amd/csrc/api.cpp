@@ -642,7 +642,7 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
   if (opts.mode != SEM_SOLVE_CG && opts.mode != SEM_SOLVE_MIXED_IR)
     return fail(SEM_EINVAL, "unknown solve mode");
   if (opts.precond != SEM_PRECOND_JACOBI && opts.precond != SEM_PRECOND_CHEBYSHEV &&
-      opts.precond != SEM_PRECOND_PMG)
+      opts.precond != SEM_PRECOND_PMG && opts.precond != SEM_PRECOND_CHEBYSHEV_FIRST)
     return fail(SEM_EINVAL, "unknown preconditioner");
   const bool pmg = opts.precond == SEM_PRECOND_PMG;
   if (pmg && !m->pmg) return fail(SEM_EINVAL, "multigrid preconditioner: call sem_setup_pmg first");
@@ -656,10 +656,11 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     return fail(SEM_EINVAL, "fixed_iters is only available in mode CG");
   if (opts.mode == SEM_SOLVE_MIXED_IR && !(opts.inner_rtol > 0.0 && opts.inner_rtol < 1.0))
     return fail(SEM_EINVAL, "inner_rtol must be in (0, 1)");
-  if (opts.precond == SEM_PRECOND_CHEBYSHEV && !prec_ok((sem_prec)opts.precond_prec))
+  const bool cheb_any =
+      opts.precond == SEM_PRECOND_CHEBYSHEV || opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST;
+  if (cheb_any && !prec_ok((sem_prec)opts.precond_prec))
     return fail(SEM_EINVAL, "unknown Chebyshev precision");
-  if (opts.mode == SEM_SOLVE_MIXED_IR && opts.precond == SEM_PRECOND_CHEBYSHEV &&
-      opts.precond_prec == SEM_FP64)
+  if (opts.mode == SEM_SOLVE_MIXED_IR && cheb_any && opts.precond_prec == SEM_FP64)
     return fail(SEM_EINVAL, "the inner solve of MIXED_IR runs in FP32 data");
 
   hipStream_t s = (hipStream_t)stream;
@@ -679,7 +680,9 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
   } guard{t0, t1};
 
   const bool neumann = m->nullspace && h2 == 0.0;
-  const bool cheb = opts.precond == SEM_PRECOND_CHEBYSHEV;
+  const bool cheb =
+      opts.precond == SEM_PRECOND_CHEBYSHEV || opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST;
+  const int kind = opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST ? 1 : 4;
   const bool pmg64 = pmg && opts.precond_prec == SEM_FP64;
   if (pmg && (st = pmg_prepare(m, k, h2, pmg64, s))) return st;
   double lmax = pmg ? m->pmg->lv[0].rho_hat : opts.lmax;
@@ -743,14 +746,16 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     } else if (cheb) {
       const int order = opts.cheb_order;
       if (opts.precond_prec == SEM_FP64) {
-        a.cheb = [op64, dinv, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
+        a.cheb = [op64, dinv, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const double* r,
                                            double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, cg, ss, ap);
+          return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, cg, ss, ap,
+                                                kind);
         };
       } else {
-        a.cheb = [opc, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const double* r,
+        a.cheb = [opc, dinv32, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const double* r,
                                             double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, float>(mm, WW, opc, dinv32, r, z, order, lmax, cg, ss, ap);
+          return cheb_apply_dev<double, float>(mm, WW, opc, dinv32, r, z, order, lmax, cg, ss, ap,
+                                               kind);
         };
       }
     }
@@ -794,9 +799,10 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
       };
     } else if (cheb) {
       const int order = opts.cheb_order;
-      a.cheb = [opc, dinv32, order, lmax](const sem_mesh* mm, SolveWork& WW, const float* rr,
+      a.cheb = [opc, dinv32, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const float* rr,
                                           float* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-        return cheb_apply_dev<float, float>(mm, WW, opc, dinv32, rr, z, order, lmax, cg, ss, ap);
+        return cheb_apply_dev<float, float>(mm, WW, opc, dinv32, rr, z, order, lmax, cg, ss, ap,
+                                            kind);
       };
     }
     a.neumann = neumann;

@@ -624,7 +624,7 @@ template sem_status apply_op<float>(const sem_mesh*, SolveWork&, const Op<float>
 template <typename Tr, typename Tp>
 sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
                           const Tr* r, Tr* z, int order, double lmax, const ChebCg& cg,
-                          hipStream_t s, int* applies) {
+                          hipStream_t s, int* applies, int kind) {
   const int64_t nf = m->n_free;
   const unsigned nb = vgrid(nf);
   Tp* d = W.vec<Tp>(sizeof(Tp) == 8 ? W.cd : W.cd32, nf);
@@ -633,7 +633,13 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
   if (!d || !rk || !wL) return fail(SEM_ENOMEM, "Chebyshev work space");
   const bool flex = cg.sc != nullptr;
   const Tr* wcg = static_cast<const Tr*>(cg.w);
-  const double c0 = 4.0 / (3.0 * lmax);
+  // fourth kind (default) or first kind on [lmax/10, lmax]: the kernels take
+  // d = c0 S r, then d = ca d + cb S r_k; only the coefficients differ
+  const bool first = (kind == 1);
+  const double lo = lmax / 10.0, theta = 0.5 * (lmax + lo), delta = 0.5 * (lmax - lo);
+  const double sigma = theta / delta;
+  double rho_prev = 1.0 / sigma;
+  const double c0 = first ? 1.0 / theta : 4.0 / (3.0 * lmax);
   Op<Tp> opk = op;
   if (flex) opk.skip = &cg.sc->done;
   else if (cg.skip_sc) opk.skip = &cg.skip_sc->done;
@@ -655,8 +661,16 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
     sem_status st = apply_op<Tp>(m, W, opk, d, wL, s, false);
     if (st) return st;
     if (applies) ++*applies;
-    const double ca = (2.0 * k - 1.0) / (2.0 * k + 3.0);
-    const double cb = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
+    double ca, cb;
+    if (first) {
+      const double rho = 1.0 / (2.0 * sigma - rho_prev);
+      ca = rho * rho_prev;
+      cb = 2.0 * rho / delta;
+      rho_prev = rho;
+    } else {
+      ca = (2.0 * k - 1.0) / (2.0 * k + 3.0);
+      cb = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
+    }
     if (flex && k == order - 1)
       hipLaunchKernelGGL((k_cheb_step<Tp, Tr, true>), dim3(nb), dim3(kVecBlock), 0, s, nf,
                          m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
@@ -671,13 +685,13 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
 }
 template sem_status cheb_apply_dev<double, double>(const sem_mesh*, SolveWork&, const Op<double>&,
                                                    const double*, const double*, double*, int,
-                                                   double, const ChebCg&, hipStream_t, int*);
+                                                   double, const ChebCg&, hipStream_t, int*, int);
 template sem_status cheb_apply_dev<double, float>(const sem_mesh*, SolveWork&, const Op<float>&,
                                                   const float*, const double*, double*, int, double,
-                                                  const ChebCg&, hipStream_t, int*);
+                                                  const ChebCg&, hipStream_t, int*, int);
 template sem_status cheb_apply_dev<float, float>(const sem_mesh*, SolveWork&, const Op<float>&,
                                                  const float*, const float*, float*, int, double,
-                                                 const ChebCg&, hipStream_t, int*);
+                                                 const ChebCg&, hipStream_t, int*, int);
 
 // ------------------------------------------------------------------- CG
 

@@ -94,7 +94,7 @@ sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* x
 template <typename Tr, typename Tp>
 sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
                           const Tr* r, Tr* z, int order, double lmax, const ChebCg& cg,
-                          hipStream_t s, int* applies);
+                          hipStream_t s, int* applies, int kind = 4);
 
 template <typename T, typename Tp>
 sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgResult& res,

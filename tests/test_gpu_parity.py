@@ -301,3 +301,25 @@ def test_graph_replayed_solve_matches_eager_launches(precond):
     xf_e, _ = sem.solve(M, b, precond=precond, max_iter=37, fixed_iters=True, profile=True)
     xf_g, _ = sem.solve(M, b, precond=precond, max_iter=37, fixed_iters=True)
     assert torch.equal(xf_e, xf_g)
+
+
+@pytest.mark.parametrize("precond_prec", ["fp64", "fp32"])
+def test_pcg_first_kind_chebyshev_matches_oracle(precond_prec):
+    """The first-kind Chebyshev variant on [rho/10, rho] (same bound as the
+    oracle's): iteration counts within 2, x within 1e-8."""
+    m, fld = config_mesh(1, N=7)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    f = fld["f"] * 3 * np.pi ** 2
+    b_or = P.rhs_from_source(f)
+    bL = sem.gs(M, sem.mass(M, dev(f)))
+    x, st = sem.solve(M, bL, precond="chebyshev1", precond_prec=precond_prec, cheb_order=4,
+                      rtol=1e-10)
+    res, xf = _true_rel_residual(P, x.cpu().numpy(), b_or)
+    ref = P.solve(b_or, rtol=1e-10, precond="chebyshev1", m=4, rho_hat=st["lmax"])
+    jac = P.solve(b_or, rtol=1e-12)
+    print(f"first-kind Chebyshev {precond_prec}: iters gpu {st['iters']} oracle {ref['iters']} "
+          f"res {res:.2e}")
+    assert st["converged"] == 1 and res <= 1e-10
+    assert abs(st["iters"] - ref["iters"]) <= 2
+    assert rel(xf, jac["x"]) <= 1e-8
