@@ -68,10 +68,20 @@ def cpu_baseline(iters):
     res = P.solve(b, rtol=1e-30, max_iter=iters, fixed_iters=True)
     dt = time.perf_counter() - t0
     gdofs = P.num.n * res["iters"] / dt / 1e9
+    cpu = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return dict(value=gdofs, unit="GDOF/s", cores=1, kind="oracle",
                 sample=(f"{res['iters']} Jacobi-PCG iterations of the NumPy oracle on a "
                         f"32x8x16-element slice of the same recipe ({P.num.n} unique nodes), "
-                        f"single-threaded einsum/bincount, {dt:.1f} s"),
+                        f"{dt:.1f} s; its einsum/bincount kernels run on one thread "
+                        f"({avail} cores available, {cpu})"),
                 seconds=dt)
 
 
@@ -342,17 +352,19 @@ def main():
     achieved = alg_bytes / (ax_avg_ms * 1e-3) / 1e9
 
     # standalone operator apply (sem_ax) rate
+    # median of individually event-timed applies after 5 warm-ups
     u = torch.randn(M.E, M.P, dtype=torch.float64, device="cuda")
     w = torch.empty_like(u)
-    for _ in range(3):
+    for _ in range(5):
         sem.ax(M, u, out=w)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.ax_reps):
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.ax_reps)]
+    for e0, e1 in evs:
+        e0.record()
         sem.ax(M, u, out=w)
-    e1.record()
+        e1.record()
     torch.cuda.synchronize()
-    sem_ax_ms = e0.elapsed_time(e1) / args.ax_reps
+    sem_ax_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
     log(f"sem_ax: {sem_ax_ms * 1e3:.1f} us, {64.0 * nL / sem_ax_ms / 1e6:.0f} GB/s")
 
     gs = gs_rate(sem, M, args.ax_reps)
