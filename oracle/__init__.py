@@ -22,7 +22,9 @@ definitions in order:
                 (Sec. 2.2), CG-Lanczos eigenvalue bound, null-space projection;
 * ``grad``      the adjoint gradient of a solve with respect to k and b;
 * ``pmg``       the p-multigrid preconditioner with Chebyshev smoothing (the
-                default pressure preconditioner named in Sec. 2.2).
+                default pressure preconditioner named in Sec. 2.2);
+* ``schwarz``   the overlapping Schwarz smoother with fast-diagonalisation
+                local solves that the p-multigrid cycle can accelerate.
 
 The paper names the method but prints none of its formulas; every function
 states the textbook definition it follows and each is pinned by a test under
@@ -36,6 +38,7 @@ from .operator import (local_apply, local_diagonal, mass_apply, kgrad_contractio
 from .assembly import Numbering, explicit_matrix, element_matrices
 from .solvers import Problem, pcg, chebyshev_apply, chebyshev1_apply, lanczos_lmax
 from .pmg import PMG, coarse_mesh, interpolation_matrix, level_orders
+from .schwarz import Schwarz, extended_1d
 from .grad import solve_and_adjoint_gradient
 
 __all__ = [
@@ -65,4 +68,6 @@ __all__ = [
     "coarse_mesh",
     "interpolation_matrix",
     "level_orders",
+    "Schwarz",
+    "extended_1d",
 ]

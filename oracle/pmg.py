@@ -186,7 +186,7 @@ class PMG:
     """The level hierarchy and the V-cycle (FP64)."""
 
     def __init__(self, xyz, gid, dirichlet, N, k=None, h2=0.0, orders=None, smooth_order=5,
-                 coarse_iters=20, coarse="cg", rho=None):
+                 coarse_iters=20, coarse="cg", rho=None, smoother="jacobi"):
         self.orders = level_orders(N) if orders is None else list(orders)
         self.m = smooth_order
         self.coarse_iters = coarse_iters
@@ -202,6 +202,22 @@ class PMG:
         self.J = [interpolation_matrix(self.orders[l + 1], self.orders[l])
                   for l in range(len(self.orders) - 1)]
         self.dinv = [1.0 / P.diag() for P in self.levels]
+        # the operator S of each smoothing level: the Jacobi diagonal, or the
+        # overlapping Schwarz smoother (its coordinates and ids per level)
+        self.smoother = smoother
+        if smoother == "jacobi":
+            self.S = list(self.dinv[:-1])
+        elif smoother == "schwarz":
+            from .schwarz import Schwarz
+            self.S = []
+            for l in range(len(self.orders) - 1):
+                if l == 0:
+                    x_l, g_l, d_l = xyz, gid, dirichlet
+                else:
+                    x_l, g_l, d_l = coarse_mesh(xyz, gid, dirichlet, N, self.orders[l])
+                self.S.append(Schwarz(x_l, g_l, d_l, self.orders[l], self.levels[l].num).apply)
+        else:
+            raise ValueError(smoother)
         if rho is not None:  # given bounds (e.g. another implementation's estimates)
             self.rho = [float(v) for v in rho]
         else:
@@ -209,7 +225,8 @@ class PMG:
             for l, P in enumerate(self.levels):
                 proj = P.project if P.neumann else None
                 v0 = np.random.default_rng(7 + l).standard_normal(P.num.n_free)
-                self.rho.append(1.1 * lanczos_lmax(P.apply, self.dinv[l], v0, 20, proj))
+                Sl = self.S[l] if l < len(self.S) else self.dinv[l]
+                self.rho.append(1.1 * lanczos_lmax(P.apply, Sl, v0, 20, proj))
         if coarse == "exact":
             from .assembly import explicit_matrix
             Pc = self.levels[-1]
@@ -242,7 +259,7 @@ class PMG:
         if l == len(self.levels) - 1:
             return self.coarse_solve(r)
         P = self.levels[l]
-        smooth = lambda v: chebyshev_apply(P.apply, self.dinv[l], v, self.m, self.rho[l])
+        smooth = lambda v: chebyshev_apply(P.apply, self.S[l], v, self.m, self.rho[l])
         x = smooth(r)
         x = x + self.prolong(l, self.vcycle(self.restrict(l, r - P.apply(x)), l + 1))
         return x + smooth(r - P.apply(x))

@@ -146,15 +146,24 @@ def pcg(A, b, M, rtol=1e-10, max_iter=10000, x0=None, fixed_iters=False,
                 beta=np.array(betas), converged=converged)
 
 
+def _as_operator(S):
+    """The preconditioner S as a function: a callable, or a diagonal given as
+    an array."""
+    return S if callable(S) else (lambda v: S * v)
+
+
 def chebyshev_apply(A, dinv, r, m, rho_hat):
-    """z = p_m(S A) S r, fourth-kind Chebyshev of order m (m-1 operator applies)."""
-    d = (4.0 / (3.0 * rho_hat)) * (dinv * r)
+    """z = p_m(S A) S r, fourth-kind Chebyshev of order m (m-1 operator
+    applies); S is the Jacobi diagonal (array) or another symmetric
+    preconditioner (callable, e.g. a Schwarz smoother)."""
+    S = _as_operator(dinv)
+    d = (4.0 / (3.0 * rho_hat)) * S(r)
     x = np.zeros_like(r)
     rk = r.copy()
     for k in range(1, m):
         x = x + d
         rk = rk - A(d)
-        d = ((2 * k - 1) / (2 * k + 3)) * d + ((8 * k + 4) / ((2 * k + 3) * rho_hat)) * (dinv * rk)
+        d = ((2 * k - 1) / (2 * k + 3)) * d + ((8 * k + 4) / ((2 * k + 3) * rho_hat)) * S(rk)
     return x + d
 
 
@@ -192,7 +201,7 @@ def lanczos_lmax(A, dinv, v0, steps=20, project=None):
     on A x = v0 through the CG-Lanczos relation: the tridiagonal T has
     T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1} = sqrt(beta_j)/alpha_j."""
     b = v0 if project is None else project(v0)
-    res = pcg(A, b, lambda r: dinv * r, rtol=0.0, max_iter=steps, fixed_iters=True,
+    res = pcg(A, b, _as_operator(dinv), rtol=0.0, max_iter=steps, fixed_iters=True,
               project=project)
     return lmax_from_cg_coefficients(res["alpha"], res["beta"])
 
