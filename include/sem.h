@@ -262,10 +262,23 @@ typedef struct {
   int32_t orders[SEM_PMG_MAX_LEVELS];  /* strictly decreasing, orders[0] = N, all >= 1 */
   int32_t smooth_order;                /* Chebyshev order m >= 1 (m-1 applies per smoothing) */
   int32_t coarse_iters;                /* Jacobi-PCG iterations on the coarsest level, >= 1 */
+  int32_t smoother;                    /* SEM_SMOOTH_JACOBI or SEM_SMOOTH_SCHWARZ */
 } sem_pmg_opts;
 
-/* Defaults: n_levels 0, smooth_order 5, coarse_iters 20 (the fastest of the
- * settings measured on the benchmark meshes to a 1e-10 residual). */
+/* The operator S the Chebyshev smoothing of a level accelerates.
+ * SEM_SMOOTH_SCHWARZ: additive overlapping Schwarz, Sec. 2.2's smoother.  The
+ * subdomain of an element is its nodes plus, across each face, the
+ * neighbour's node layer one GLL step inside; the local problem on that
+ * (N+3)^3 box is the separable approximation built from three 1-D GLL
+ * elements (the element and its two neighbours along each direction, at
+ * their mean lengths), solved exactly by fast diagonalisation; the box's
+ * edge and corner points are left out.  The local operator is that of the
+ * constant-coefficient Laplacian whatever k and h2 (the Chebyshev bound, a
+ * Lanczos estimate of the Schwarz-preconditioned operator, absorbs the
+ * scale). */
+typedef enum { SEM_SMOOTH_JACOBI = 0, SEM_SMOOTH_SCHWARZ = 1 } sem_smoother;
+
+/* Defaults: n_levels 0, smooth_order 5, coarse_iters 20, Jacobi smoother. */
 void sem_pmg_opts_default(sem_pmg_opts* opts);
 
 /* Build (or rebuild) the hierarchy of `mesh` from the description it was set
@@ -288,6 +301,14 @@ sem_status sem_pmg_info(const sem_mesh* mesh, int32_t* n_levels, int32_t* orders
  * cycle).  Blocks on the first call for given k, h2 (level bounds). */
 sem_status sem_pmg_apply(const sem_mesh* mesh, const double* r, double* z, const double* k,
                          double h2, sem_prec prec, void* stream);
+
+/* HOST-only.  The Schwarz subdomains sem_setup_pmg builds for an order-N
+ * mesh (1 <= N <= 10; same validation as sem_setup_mesh), with the free
+ * numbering of sem_host_numbering: xmap [E][(N+3)^3] receives the free index
+ * of each box point or -1; S [E][3][(N+3)^2] (row-major per direction r, s,
+ * t) and lam [E][3][N+3] the fast-diagonalisation factors (nullable). */
+sem_status sem_host_schwarz(int32_t N, int64_t E, const int64_t* gid, const uint8_t* dirichlet,
+                            const double* xyz, int32_t* xmap, double* S, double* lam);
 
 /* HOST-only.  The order-Nc mesh sem_setup_pmg builds from an order-N one
  * (2 <= N <= 10, 1 <= Nc < N): xyz_c [E][Pc][3] (nullable together with

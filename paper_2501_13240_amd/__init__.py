@@ -19,6 +19,7 @@ from .api import (
     gs,
     host_coarse_mesh,
     host_numbering,
+    host_schwarz,
     jacobi_inverse,
     lmax_estimate,
     mask,
@@ -43,6 +44,7 @@ __all__ = [
     "gs",
     "host_coarse_mesh",
     "host_numbering",
+    "host_schwarz",
     "jacobi_inverse",
     "lmax_estimate",
     "mask",

@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_ENOMEM", -3: "SEM_EDEVIC
 PREC = {"fp64": 0, "fp32": 1, "bf16_mfma": 2, "fp16_mfma": 3}
 PRECOND = {"jacobi": 0, "chebyshev": 1, "pmg": 2, "chebyshev1": 3}
 PMG_MAX_LEVELS = 8
+SMOOTHER = {"jacobi": 0, "schwarz": 1}
 MODE = {"cg": 0, "mixed_ir": 1}
 
 
@@ -56,7 +57,7 @@ class SolveStats(ctypes.Structure):
 
 class PmgOpts(ctypes.Structure):
     _fields_ = [("n_levels", c_int32), ("orders", c_int32 * 8), ("smooth_order", c_int32),
-                ("coarse_iters", c_int32)]
+                ("coarse_iters", c_int32), ("smoother", c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -84,6 +85,8 @@ SIGNATURES = {
                                 c_void_p]),
     "sem_host_coarse_mesh": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_int32,
                                        c_void_p, c_void_p, c_void_p]),
+    "sem_host_schwarz": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p]),
     "sem_lmax_estimate": (c_int32, [c_void_p, c_void_p, c_double, c_int32,
                                     ctypes.POINTER(c_double), c_void_p]),
     "sem_pcg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,

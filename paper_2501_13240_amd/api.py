@@ -95,9 +95,10 @@ class Mesh:
     def handle(self):
         return self._h
 
-    def setup_pmg(self, orders=None, smooth_order: int = 5, coarse_iters: int = 20):
+    def setup_pmg(self, orders=None, smooth_order: int = 5, coarse_iters: int = 20,
+                  smoother: str = "jacobi"):
         """Build the p-multigrid hierarchy (sem_setup_pmg); orders default to
-        N, N//2, ..., 1."""
+        N, N//2, ..., 1; smoother 'jacobi' or 'schwarz'."""
         opts = L.PmgOpts()
         self._lib.sem_pmg_opts_default(ctypes.byref(opts))
         if orders is not None:
@@ -107,6 +108,7 @@ class Mesh:
                 opts.orders[i] = o
         opts.smooth_order = int(smooth_order)
         opts.coarse_iters = int(coarse_iters)
+        opts.smoother = L.SMOOTHER[smoother]
         xyz, gid, d = self._desc_arrays
         desc = L.MeshDesc(self.N, self.E, _np_ptr(xyz), _np_ptr(gid), _np_ptr(d))
         _check(self._lib.sem_setup_pmg(self._h, ctypes.byref(desc), ctypes.byref(opts), _stream()),
@@ -247,6 +249,23 @@ def host_coarse_mesh(N: int, gid: np.ndarray, dirichlet, xyz, Nc: int):
                                     _np_ptr(gid_c), _np_ptr(d_c), _np_ptr(x_c)),
            "sem_host_coarse_mesh")
     return x_c, gid_c, d_c
+
+
+def host_schwarz(N: int, gid: np.ndarray, dirichlet, xyz):
+    """The library's Schwarz subdomain map and fast-diagonalisation factors
+    (host): xmap (E, (N+3)^3), S (E, 3, N+3, N+3), lam (E, 3, N+3)."""
+    lib = L.load()
+    gid = np.ascontiguousarray(gid, dtype=np.int64)
+    E = gid.shape[0]
+    nx = N + 3
+    d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    x = np.ascontiguousarray(xyz, dtype=np.float64)
+    xmap = np.empty((E, nx ** 3), dtype=np.int32)
+    S = np.empty((E, 3, nx, nx))
+    lam = np.empty((E, 3, nx))
+    _check(lib.sem_host_schwarz(N, E, _np_ptr(gid), _np_ptr(d), _np_ptr(x), _np_ptr(xmap),
+                                _np_ptr(S), _np_ptr(lam)), "sem_host_schwarz")
+    return xmap, S, lam
 
 
 def lmax_estimate(mesh: Mesh, k=None, h2: float = 0.0, steps: int = 20) -> float:

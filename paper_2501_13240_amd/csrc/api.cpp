@@ -188,6 +188,9 @@ static sem_status estimate_lmax(const sem_mesh* m, SolveWork& W, const double* k
 // allocation happens inside the iterations (which may be graph-captured).
 // Must run before the caller places its own vectors in the fine work space:
 // the bound estimate uses it.
+static sem_status estimate_lmax_schwarz(Pmg& P, int l, const double* k, double h2, double* out,
+                                        hipStream_t s);
+
 static sem_status pmg_prepare(const sem_mesh* m, const double* k, double h2, bool f64,
                               hipStream_t s) {
   Pmg& P = *m->pmg;
@@ -208,14 +211,19 @@ static sem_status pmg_prepare(const sem_mesh* m, const double* k, double h2, boo
     }
     if ((st = prepare_dinv(ml, Wl, kl, h2, s))) return st;
     double est = 0.0;
-    if ((st = estimate_lmax(ml, Wl, kl, h2, 20, &est, s))) return st;
+    const bool schwarz = P.smoother == SEM_SMOOTH_SCHWARZ && l + 1 < P.lv.size();
+    if (schwarz) {
+      if ((st = estimate_lmax_schwarz(P, (int)l, kl, h2, &est, s))) return st;
+    } else if ((st = estimate_lmax(ml, Wl, kl, h2, 20, &est, s))) {
+      return st;
+    }
     L.rho_hat = 1.1 * est;
     L.op64 = op64_of(ml, kl, h2);
     if ((st = op32_of(ml, Wl, kl, h2, s, L.op32))) return st;
     L.dinv64 = Wl.dinv.as<double>();
     L.dinv32 = Wl.dinv32.as<float>();
     bool ok = true;
-    for (int v = 0; v < 5; ++v) ok = ok && (f64 ? P.vec<double>(L, v) != nullptr : P.vec<float>(L, v) != nullptr);
+    for (int v = 0; v < 8; ++v) ok = ok && (f64 ? P.vec<double>(L, v) != nullptr : P.vec<float>(L, v) != nullptr);
     if (f64)
       ok = ok && Wl.vec<double>(Wl.wL, ml->nL) && Wl.vec<double>(Wl.cd, ml->n_free) &&
            Wl.vec<double>(Wl.crk, ml->n_free);
@@ -225,6 +233,94 @@ static sem_status pmg_prepare(const sem_mesh* m, const double* k, double h2, boo
     if (!ok) return fail(SEM_ENOMEM, "multigrid work space");
   }
   SEM_HIP(hipStreamSynchronize(s));
+  return SEM_OK;
+}
+
+// Schwarz factors of one level on the device (from its host description)
+static sem_status setup_schwarz(PmgLevel& L, int N, int64_t E, const int64_t* gid,
+                                const uint8_t* dir, const double* xyz, hipStream_t s) {
+  HostNumbering hn;
+  sem_status st = build_numbering(N, E, gid, dir, hn);
+  if (st) return st;
+  SchwarzHost H;
+  if ((st = build_schwarz(N, E, gid, dir, xyz, hn.lmap.data(), hn.n_free, H))) return st;
+  SchwarzDev& X = L.sch;
+  X.nx = N + 3;
+  std::vector<float> S32(H.S.begin(), H.S.end()), L32(H.lam.begin(), H.lam.end());
+  if ((st = upload(X.xmap, H.xmap, s)) || (st = upload(X.xseg, H.xseg, s)) ||
+      (st = upload(X.xperm, H.xperm, s)) || (st = upload(X.S64, H.S, s)) ||
+      (st = upload(X.S32, S32, s)) || (st = upload(X.L64, H.lam, s)) ||
+      (st = upload(X.L32, L32, s)))
+    return st;
+  const size_t nbox = H.xmap.size();
+  if ((st = X.box64.ensure(nbox * sizeof(double))) || (st = X.box32.ensure(nbox * sizeof(float))))
+    return st;
+  SEM_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+  return SEM_OK;
+}
+
+// largest eigenvalue of (Schwarz) A on a level from 20 CG-Lanczos steps with
+// the Schwarz smoother as preconditioner (cached per level for k == NULL)
+static sem_status estimate_lmax_schwarz(Pmg& P, int l, const double* k, double h2, double* out,
+                                        hipStream_t s) {
+  PmgLevel& L = P.lv[l];
+  const sem_mesh* ml = L.m;
+  if (!k && L.sch_rho > 0.0 && L.sch_rho_h2 == h2) {
+    *out = L.sch_rho;
+    return SEM_OK;
+  }
+  SolveWork& W = work_of(ml);
+  sem_status st = W.init(ml, 20);
+  if (st) return st;
+  if ((st = prepare_dinv(ml, W, k, h2, s))) return st;
+  const bool neumann = ml->nullspace && h2 == 0.0;
+  const int64_t nf = ml->n_free;
+  double* b = W.vec<double>(W.tmpf, nf);
+  CgArgs<double, double> a;
+  a.op = op64_of(ml, k, h2);
+  a.b = b;
+  a.x = W.vec<double>(W.x, nf);
+  a.r = W.vec<double>(W.r, nf);
+  a.p = W.vec<double>(W.p, nf);
+  a.w = W.vec<double>(W.w, nf);
+  a.z = W.vec<double>(W.z, nf);
+  a.wL = W.vec<double>(W.wL, ml->nL);
+  a.dinv = W.dinv.as<double>();
+  if (!b || !a.x || !a.r || !a.p || !a.w || !a.z || !a.wL || !P.vec<double>(L, 7))
+    return fail(SEM_ENOMEM, "work space");
+  SEM_HIP(launch_pseudo_random(b, nf, 0x5eed5eedull, s));
+  if (neumann && (st = free_remove_mean_f64(ml, W, b, s))) return st;
+  a.precond = SEM_PRECOND_CHEBYSHEV;  // the flexible path, preconditioned by:
+  Pmg* pp = &P;
+  a.cheb = [pp, l](const sem_mesh*, SolveWork&, const double* r, double* z, const ChebCg& cg,
+                   hipStream_t ss, int*) { return schwarz_precond(*pp, l, r, z, cg, ss); };
+  a.rtol = 0.0;
+  a.max_it = 20;
+  a.fixed = true;
+  a.x_zero = true;
+  a.neumann = neumann;
+  std::vector<double> al, be;
+  a.alpha_out = &al;
+  a.beta_out = &be;
+  CgResult res;
+  if ((st = cg_solve<double, double>(ml, W, a, res, s))) return st;
+  int n = (int)al.size();
+  for (int j = 0; j < n; ++j)
+    if (!(al[j] > 0.0) || !std::isfinite(al[j])) {
+      n = j;
+      break;
+    }
+  if (n == 0) return fail(SEM_EBREAKDOWN, "Schwarz bound: CG produced no coefficient");
+  std::vector<double> diag(n), off(std::max(n - 1, 0));
+  for (int j = 0; j < n; ++j) {
+    diag[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < n) off[j] = std::sqrt(std::max(be[j], 0.0)) / al[j];
+  }
+  *out = tridiag_lmax(diag, off);
+  if (!k) {
+    L.sch_rho = *out;
+    L.sch_rho_h2 = h2;
+  }
   return SEM_OK;
 }
 
@@ -503,6 +599,7 @@ void sem_pmg_opts_default(sem_pmg_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->smooth_order = 5;
   o->coarse_iters = 20;
+  o->smoother = SEM_SMOOTH_JACOBI;
 }
 
 sem_status sem_setup_pmg(sem_mesh* m, const sem_mesh_desc* desc, const sem_pmg_opts* opts_in,
@@ -516,6 +613,8 @@ sem_status sem_setup_pmg(sem_mesh* m, const sem_mesh_desc* desc, const sem_pmg_o
   else sem_pmg_opts_default(&opts);
   if (opts.smooth_order < 1) return fail(SEM_EINVAL, "smooth_order must be >= 1");
   if (opts.coarse_iters < 1) return fail(SEM_EINVAL, "coarse_iters must be >= 1");
+  if (opts.smoother != SEM_SMOOTH_JACOBI && opts.smoother != SEM_SMOOTH_SCHWARZ)
+    return fail(SEM_EINVAL, "unknown smoother");
   std::vector<int> orders;
   if (opts.n_levels == 0) {
     for (int n = m->N; ; n /= 2) {
@@ -535,14 +634,19 @@ sem_status sem_setup_pmg(sem_mesh* m, const sem_mesh_desc* desc, const sem_pmg_o
   std::unique_ptr<Pmg, void (*)(Pmg*)> P(new Pmg(), pmg_destroy);
   P->smooth_order = opts.smooth_order;
   P->coarse_iters = opts.coarse_iters;
+  P->smoother = opts.smoother;
   P->lv.resize(orders.size());
   const int64_t E = m->E;
   sem_status st;
   for (size_t l = 0; l < orders.size(); ++l) {
     PmgLevel& L = P->lv[l];
     L.N = orders[l];
+    const bool smooths = l + 1 < orders.size();
     if (l == 0) {
       L.m = m;
+      if (smooths && opts.smoother == SEM_SMOOTH_SCHWARZ &&
+          (st = setup_schwarz(L, desc->N, E, desc->gid, desc->dirichlet, desc->xyz, s)))
+        return st;
       continue;
     }
     const int Nc = orders[l];
@@ -558,6 +662,10 @@ sem_status sem_setup_pmg(sem_mesh* m, const sem_mesh_desc* desc, const sem_pmg_o
     if ((st = sem_setup_mesh(&dc, stream, &mc))) return st;
     L.m = mc;
     L.owned = true;
+    if (smooths && opts.smoother == SEM_SMOOTH_SCHWARZ &&
+        (st = setup_schwarz(L, Nc, E, gid_c.data(), desc->dirichlet ? dir_c.data() : nullptr,
+                            xyz_c.data(), s)))
+      return st;
     std::vector<double> Ik((size_t)(Nc + 1) * (m->N + 1));
     if ((st = host_interp_matrix(m->N, Nc, Ik.data())) || (st = upload(L.Ik64, Ik, s))) return st;
   }
@@ -610,6 +718,20 @@ sem_status sem_pmg_apply(const sem_mesh* m, const double* r, double* z, const do
   else st = pmg_precond<double, float>(m, W, rf, zf, ChebCg(), s, nullptr);
   if (st) return st;
   SEM_HIP((launch_free_to_local<double, double>(m, zf, z, s)));
+  return SEM_OK;
+}
+
+sem_status sem_host_schwarz(int32_t N, int64_t E, const int64_t* gid, const uint8_t* dirichlet,
+                            const double* xyz, int32_t* xmap, double* S, double* lam) {
+  if (!gid || !xyz || !xmap) return fail(SEM_EINVAL, "gid, xyz and xmap are required");
+  HostNumbering hn;
+  sem_status st = build_numbering(N, E, gid, dirichlet, hn);
+  if (st) return st;
+  SchwarzHost H;
+  if ((st = build_schwarz(N, E, gid, dirichlet, xyz, hn.lmap.data(), hn.n_free, H))) return st;
+  std::memcpy(xmap, H.xmap.data(), H.xmap.size() * sizeof(int32_t));
+  if (S) std::memcpy(S, H.S.data(), H.S.size() * sizeof(double));
+  if (lam) std::memcpy(lam, H.lam.data(), H.lam.size() * sizeof(double));
   return SEM_OK;
 }
 

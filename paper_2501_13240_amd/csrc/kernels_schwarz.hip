@@ -1,0 +1,153 @@
+// Fast-diagonalisation local solves of the overlapping Schwarz smoother.
+//
+// One element per workgroup: the residual is gathered into the element's
+// (N+3)^3 box through its subdomain map (0 at points outside the
+// subdomain), transformed by S_r^T, S_s^T, S_t^T along the three directions,
+// divided by l_r,i + l_s,j + l_t,k, transformed back by S_t, S_s, S_r, and
+// written to the box buffer; a segmented sum over the box points of each
+// free node completes z = sum_e R_e^T A~_e^{-1} R_e r.  Each 1-D transform of
+// the box is a batch of 16-column tiles C = M X on the matrix cores (16x16x4
+// MFMA in FP64 or FP32) with M = S or S^T of this element, read from LDS.
+#include "schwarz.hpp"
+
+namespace sem {
+namespace {
+
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+// 16x16x4 MFMA: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; result
+// (i, j) in lane 16 (i % 4) + j, register i / 4 (FP64) or lane 16 (i / 4) + j,
+// register i % 4 (FP32)
+template <typename T>
+struct Mm;
+template <>
+struct Mm<double> {
+  typedef v4d_t V;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mm<float> {
+  typedef v4f_t V;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// one 16-column tile of dst = M src along direction DIR of an n^3 box
+// ([k][j][i]); M = S^T (TRANS) or S, S row-major n x n in LDS
+template <int n, typename T, int DIR, bool TRANS>
+__device__ __forceinline__ void fdm_tile(const T* __restrict__ src, T* __restrict__ dst,
+                                         const T* __restrict__ S, int tile, int lane) {
+  constexpr int P2 = n * n, KS = (n + 3) / 4;
+  const int col = tile * 16 + (lane & 15);
+  const int kk = lane >> 4, mrow = lane & 15;
+  const bool cval = col < P2;
+  const int c1 = cval ? col / n : 0, c0 = cval ? col % n : 0;
+  typename Mm<T>::V acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int l = 4 * s + kk;
+    T a = T(0), b = T(0);
+    if (mrow < n && l < n) a = TRANS ? S[l * n + mrow] : S[mrow * n + l];
+    if (cval && l < n) {
+      const int ad = DIR == 0 ? c1 * P2 + c0 * n + l : DIR == 1 ? c1 * P2 + l * n + c0 : l * P2 + col;
+      b = src[ad];
+    }
+    acc = Mm<T>::mma(a, b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = Mm<T>::row(lane, r);
+    if (cval && row < n) {
+      const int ad =
+          DIR == 0 ? c1 * P2 + c0 * n + row : DIR == 1 ? c1 * P2 + row * n + c0 : row * P2 + col;
+      dst[ad] = acc[r];
+    }
+  }
+}
+
+constexpr int kFdmThreads = 256;
+
+template <int n, typename T>
+__global__ __launch_bounds__(kFdmThreads) void fdm_kernel(const int32_t* __restrict__ xmap,
+                                                          const T* __restrict__ S,
+                                                          const T* __restrict__ lam,
+                                                          const T* __restrict__ r,
+                                                          T* __restrict__ out,
+                                                          const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int P2 = n * n, P3 = P2 * n, NT = (P2 + 15) / 16, NW = kFdmThreads / 64;
+  __shared__ T sA[P3];
+  __shared__ T sB[P3];
+  __shared__ T sS[3][P2];
+  __shared__ T sL[3][n];
+  const int64_t e = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int q = t; q < 3 * P2; q += kFdmThreads) (&sS[0][0])[q] = S[e * 3 * P2 + q];
+  for (int q = t; q < 3 * n; q += kFdmThreads) (&sL[0][0])[q] = lam[e * 3 * n + q];
+  for (int q = t; q < P3; q += kFdmThreads) {
+    const int32_t g = xmap[e * P3 + q];
+    sA[q] = g >= 0 ? r[g] : T(0);
+  }
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 0, true>(sA, sB, sS[0], tile, lane);
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 1, true>(sB, sA, sS[1], tile, lane);
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 2, true>(sA, sB, sS[2], tile, lane);
+  __syncthreads();
+  for (int q = t; q < P3; q += kFdmThreads) {
+    const int a = q % n, b = (q / n) % n, c = q / P2;
+    sB[q] = sB[q] / (sL[0][a] + sL[1][b] + sL[2][c]);
+  }
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 2, false>(sB, sA, sS[2], tile, lane);
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 1, false>(sA, sB, sS[1], tile, lane);
+  __syncthreads();
+  for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 0, false>(sB, sA, sS[0], tile, lane);
+  __syncthreads();
+  for (int q = t; q < P3; q += kFdmThreads) out[e * P3 + q] = sA[q];
+}
+
+template <int n, typename T>
+hipError_t run_fdm(int64_t E, const int32_t* xmap, const T* S, const T* lam, const T* r, T* out,
+                   const int32_t* skip, hipStream_t s) {
+  hipLaunchKernelGGL((fdm_kernel<n, T>), dim3((unsigned)E), dim3(kFdmThreads), 0, s, xmap, S, lam,
+                     r, out, skip);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fdm(const SchwarzDev& X, int64_t E, const T* r, T* box_out,
+                      const int32_t* skip, hipStream_t s) {
+  const int32_t* xm = X.xmap.as<int32_t>();
+  const T* S = sizeof(T) == 8 ? (const T*)X.S64.p : (const T*)X.S32.p;
+  const T* L = sizeof(T) == 8 ? (const T*)X.L64.p : (const T*)X.L32.p;
+  switch (X.nx) {
+    case 4: return run_fdm<4, T>(E, xm, S, L, r, box_out, skip, s);
+    case 5: return run_fdm<5, T>(E, xm, S, L, r, box_out, skip, s);
+    case 6: return run_fdm<6, T>(E, xm, S, L, r, box_out, skip, s);
+    case 7: return run_fdm<7, T>(E, xm, S, L, r, box_out, skip, s);
+    case 8: return run_fdm<8, T>(E, xm, S, L, r, box_out, skip, s);
+    case 9: return run_fdm<9, T>(E, xm, S, L, r, box_out, skip, s);
+    case 10: return run_fdm<10, T>(E, xm, S, L, r, box_out, skip, s);
+    case 11: return run_fdm<11, T>(E, xm, S, L, r, box_out, skip, s);
+    case 12: return run_fdm<12, T>(E, xm, S, L, r, box_out, skip, s);
+    case 13: return run_fdm<13, T>(E, xm, S, L, r, box_out, skip, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_fdm<double>(const SchwarzDev&, int64_t, const double*, double*,
+                                       const int32_t*, hipStream_t);
+template hipError_t launch_fdm<float>(const SchwarzDev&, int64_t, const float*, float*,
+                                      const int32_t*, hipStream_t);
+
+}  // namespace sem

@@ -110,6 +110,15 @@ __global__ void k_seg_sub(int64_t nf, const int32_t* __restrict__ seg,
   GRID_STRIDE(g, nf) r[g] = b[g] - segment_sum<T>(perm, vL, seg[g], seg[g + 1]);
 }
 
+// r[g] -= sum of the copies of free node g (in place)
+template <typename T>
+__global__ void k_seg_dec(int64_t nf, const int32_t* __restrict__ seg,
+                          const int32_t* __restrict__ perm, const T* __restrict__ vL,
+                          T* __restrict__ r, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  GRID_STRIDE(g, nf) r[g] -= segment_sum<T>(perm, vL, seg[g], seg[g + 1]);
+}
+
 template <typename T>
 __global__ void k_vadd(int64_t n, T* __restrict__ x, const T* __restrict__ y,
                        const int32_t* __restrict__ skip) {
@@ -146,6 +155,96 @@ T* local_scratch(const sem_mesh* m) {
   return W.vec<T>(sizeof(T) == 8 ? W.wL : W.wL32, m->nL);
 }
 
+// Chebyshev-Schwarz kernels: the fourth-kind recurrence with S = Schwarz
+template <typename T>
+__global__ void k_schw_init(int64_t nf, const T* __restrict__ r, const T* __restrict__ q,
+                            T* __restrict__ d, T* __restrict__ rk, T* __restrict__ z, T c0,
+                            const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  GRID_STRIDE(g, nf) {
+    const T dg = c0 * q[g];
+    d[g] = dg;
+    rk[g] = r[g];
+    z[g] = dg;
+  }
+}
+
+template <typename T>
+__global__ void k_schw_step(int64_t nf, const T* __restrict__ q, T* __restrict__ d,
+                            T* __restrict__ z, T ca, T cb, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  GRID_STRIDE(g, nf) {
+    const T dg = ca * d[g] + cb * q[g];
+    d[g] = dg;
+    z[g] += dg;
+  }
+}
+
+template <typename T>
+T* box_of(const SchwarzDev& X) {
+  if constexpr (sizeof(T) == 8) return X.box64.as<double>();
+  else return X.box32.as<float>();
+}
+
+// z = S r: local fast-diagonalisation solves, then the sum over box copies
+template <typename T>
+sem_status schwarz_apply(const PmgLevel& L, const T* r, T* z, const int32_t* skip,
+                         hipStream_t s) {
+  const sem_mesh* m = L.m;
+  T* box = box_of<T>(L.sch);
+  if (!box) return fail(SEM_EINVAL, "Schwarz factors missing");
+  SEM_HIP(launch_fdm<T>(L.sch, m->E, r, box, skip, s));
+  hipLaunchKernelGGL((k_seg_sum<T>), dim3(grid_for(m->n_free)), dim3(kVecBlock), 0, s, m->n_free,
+                     L.sch.xseg.as<int32_t>(), L.sch.xperm.as<int32_t>(), box, z, skip);
+  SEM_CHECK_LAUNCH("Schwarz sum");
+  return SEM_OK;
+}
+
+// z = p_m(S A) S r with the fourth-kind coefficients (as the Jacobi version)
+template <typename T>
+sem_status cheb_schwarz(Pmg& P, PmgLevel& L, const T* r, T* z, const CgScalars* outer,
+                        hipStream_t s, int* applies) {
+  const sem_mesh* m = L.m;
+  SolveWork& W = *m->work;
+  const int64_t nf = m->n_free;
+  const int32_t* skip = outer ? &outer->done : nullptr;
+  T* d = P.vec<T>(L, 5);
+  T* rk = P.vec<T>(L, 6);
+  T* q = P.vec<T>(L, 7);
+  T* wL = local_scratch<T>(m);
+  if (!d || !rk || !q || !wL) return fail(SEM_ENOMEM, "multigrid work space");
+  Op<T> op = op_of<T>(L);
+  op.skip = skip;
+  const double lmax = L.rho_hat;
+  sem_status st;
+  if ((st = schwarz_apply<T>(L, r, q, skip, s))) return st;
+  hipLaunchKernelGGL((k_schw_init<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf, r, q, d, rk,
+                     z, (T)(4.0 / (3.0 * lmax)), skip);
+  for (int k = 1; k < P.smooth_order; ++k) {
+    if ((st = apply_op<T>(m, W, op, d, wL, s, false))) return st;
+    if (applies) ++*applies;
+    hipLaunchKernelGGL((k_seg_dec<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
+                       m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, skip);
+    if ((st = schwarz_apply<T>(L, rk, q, skip, s))) return st;
+    const double ca = (2.0 * k - 1.0) / (2.0 * k + 3.0);
+    const double cb = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
+    hipLaunchKernelGGL((k_schw_step<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf, q, d, z,
+                       (T)ca, (T)cb, skip);
+  }
+  SEM_CHECK_LAUNCH("Chebyshev-Schwarz");
+  return SEM_OK;
+}
+
+template <typename T>
+sem_status smooth(Pmg& P, PmgLevel& L, const T* r, T* z, const CgScalars* outer, hipStream_t s,
+                  int* applies) {
+  if (P.smoother == 1) return cheb_schwarz<T>(P, L, r, z, outer, s, applies);
+  ChebCg c;
+  c.skip_sc = outer;
+  return cheb_apply_dev<T, T>(L.m, *L.m->work, op_of<T>(L), dinv_of<T>(L), r, z, P.smooth_order,
+                              L.rho_hat, c, s, applies);
+}
+
 template <typename T>
 sem_status vcycle(Pmg& P, int l, const T* r, T* x, const CgScalars* outer, hipStream_t s,
                   int* applies) {
@@ -167,15 +266,11 @@ sem_status vcycle(Pmg& P, int l, const T* r, T* x, const CgScalars* outer, hipSt
     return cg_fixed_device<T>(m, W, op, dinv, r, x, t, u, w, wL, P.coarse_iters,
                               m->nullspace && op.h2 == T(0), outer, s);
   }
-  ChebCg smooth;
-  smooth.skip_sc = outer;
   Op<T> ops = op;
   ops.skip = skip;
   sem_status st;
   // pre-smoothing
-  if ((st = cheb_apply_dev<T, T>(m, W, op, dinv, r, x, P.smooth_order, L.rho_hat, smooth, s,
-                                 applies)))
-    return st;
+  if ((st = smooth<T>(P, L, r, x, outer, s, applies))) return st;
   // t = r - A x, restricted to the next level
   if ((st = apply_op<T>(m, W, ops, x, wL, s, false))) return st;
   if (applies) ++*applies;
@@ -204,9 +299,7 @@ sem_status vcycle(Pmg& P, int l, const T* r, T* x, const CgScalars* outer, hipSt
   if (applies) ++*applies;
   hipLaunchKernelGGL((k_seg_sub<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
                      m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, r, t, skip);
-  if ((st = cheb_apply_dev<T, T>(m, W, op, dinv, t, u, P.smooth_order, L.rho_hat, smooth, s,
-                                 applies)))
-    return st;
+  if ((st = smooth<T>(P, L, t, u, outer, s, applies))) return st;
   hipLaunchKernelGGL((k_vadd<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf, x, u, skip);
   SEM_CHECK_LAUNCH("post-smoothing");
   return SEM_OK;
@@ -216,8 +309,8 @@ sem_status vcycle(Pmg& P, int l, const T* r, T* x, const CgScalars* outer, hipSt
 
 template <typename T>
 T* Pmg::vec(PmgLevel& L, int which) {
-  DevBuf* b64[5] = {&L.r64, &L.x64, &L.t64, &L.u64, &L.w64};
-  DevBuf* b32[5] = {&L.r32, &L.x32, &L.t32, &L.u32, &L.w32};
+  DevBuf* b64[8] = {&L.r64, &L.x64, &L.t64, &L.u64, &L.w64, &L.d64, &L.k64v, &L.q64};
+  DevBuf* b32[8] = {&L.r32, &L.x32, &L.t32, &L.u32, &L.w32, &L.d32, &L.k32v, &L.q32};
   DevBuf& b = sizeof(T) == 8 ? *b64[which] : *b32[which];
   if (b.ensure((size_t)std::max<int64_t>(L.m->n_free, 1) * sizeof(T)) != SEM_OK) return nullptr;
   return b.as<T>();
@@ -288,5 +381,18 @@ template sem_status pmg_precond<double, float>(const sem_mesh*, SolveWork&, cons
                                                double*, const ChebCg&, hipStream_t, int*);
 template sem_status pmg_precond<float, float>(const sem_mesh*, SolveWork&, const float*, float*,
                                               const ChebCg&, hipStream_t, int*);
+
+sem_status schwarz_precond(Pmg& P, int level, const double* r, double* z, const ChebCg& cg,
+                           hipStream_t s) {
+  PmgLevel& L = P.lv[level];
+  const int64_t nf = L.m->n_free;
+  sem_status st;
+  if (cg.sc && (st = launch_cg_gate(cg.check_in, cg.nblk, cg.sc, cg.hist, s))) return st;
+  double* q = P.vec<double>(L, 7);
+  if (!q) return fail(SEM_ENOMEM, "multigrid work space");
+  if ((st = schwarz_apply<double>(L, r, q, cg.sc ? &cg.sc->done : nullptr, s))) return st;
+  return launch_flex_dots<double, double>(nf, q, z, r, static_cast<const double*>(cg.w),
+                                          cg.part_out, cg.sc, s);
+}
 
 }  // namespace sem

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "schwarz.hpp"
 #include "solver.hpp"
 
 namespace sem {
@@ -22,8 +23,12 @@ struct PmgLevel {
   // interpolation from level l+1 to level l, (N_l+1) x (N_{l+1}+1) row-major,
   // and its transpose (restriction), in both precisions
   DevBuf J64, J32, JT64, JT32;
-  // free vectors of this level: r (input), x (output), t, u (scratch)
-  DevBuf r64, x64, t64, u64, w64, r32, x32, t32, u32, w32;
+  // free vectors of this level: r (input), x (output), t, u, w (scratch),
+  // d, rk, q (Chebyshev-Schwarz smoothing)
+  DevBuf r64, x64, t64, u64, w64, d64, k64v, q64, r32, x32, t32, u32, w32, d32, k32v, q32;
+  SchwarzDev sch;          // Schwarz factors (levels that smooth, Schwarz smoother only)
+  double sch_rho = 0.0;    // cached bound of the Schwarz-preconditioned operator (k == NULL)
+  double sch_rho_h2 = -1.0;
   DevBuf Ik64;  // interpolation from level 0's GLL points to this level's (levels >= 1)
   DevBuf k64;   // k interpolated to this level (levels >= 1, per solve)
   // per solve
@@ -36,10 +41,11 @@ struct PmgLevel {
 
 struct Pmg {
   std::vector<PmgLevel> lv;
-  int smooth_order = 3;
-  int coarse_iters = 30;
+  int smooth_order = 5;
+  int coarse_iters = 20;
+  int smoother = 0;  // 0 Jacobi, 1 overlapping Schwarz
   template <typename T>
-  T* vec(PmgLevel& L, int which);  // 0 r, 1 x, 2 t, 3 u, 4 w
+  T* vec(PmgLevel& L, int which);  // 0 r, 1 x, 2 t, 3 u, 4 w, 5 d, 6 rk, 7 q
 };
 
 void pmg_destroy(Pmg* p);
@@ -71,5 +77,10 @@ hipError_t launch_interp(int64_t E, int n_in, int n_out, const T* M, int mode, c
 template <typename Tr, typename Tp>
 sem_status pmg_precond(const sem_mesh* m, SolveWork& W, const Tr* r, Tr* z, const ChebCg& cg,
                        hipStream_t s, int* applies);
+
+// The Schwarz smoother of one level as a flexible-CG preconditioner (for the
+// Lanczos bound of the Schwarz-preconditioned operator): z = S r.
+sem_status schwarz_precond(Pmg& P, int level, const double* r, double* z, const ChebCg& cg,
+                           hipStream_t s);
 
 }  // namespace sem

@@ -34,9 +34,9 @@ def dev(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def _vcycle_case(m, N, k=None, h2=0.0, seed=1):
+def _vcycle_case(m, N, k=None, h2=0.0, seed=1, smoother="jacobi"):
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
-    M.setup_pmg()
+    M.setup_pmg(smoother=smoother)
     orders, _ = M.pmg_info()
     assert orders == level_orders(N)
     kd = None if k is None else dev(k)
@@ -48,13 +48,14 @@ def _vcycle_case(m, N, k=None, h2=0.0, seed=1):
     z64 = sem.pmg_apply(M, rL, k=kd, h2=h2, prec="fp64").cpu().numpy()
     _, rho = M.pmg_info()
     z32 = sem.pmg_apply(M, rL, k=kd, h2=h2, prec="fp32").cpu().numpy()
-    pmg = PMG(m.xyz, m.gid, m.dirichlet, N, k=k, h2=h2, rho=rho)
+    pmg = PMG(m.xyz, m.gid, m.dirichlet, N, k=k, h2=h2, rho=rho, smoother=smoother)
     z_or = P0.num.to_local(pmg.vcycle(rf))
     if P0.neumann:  # the cycle's output is defined up to a constant on a singular level
         mean = lambda zl: P0.num.from_local_consistent(zl).mean()
         z64, z32, z_or = z64 - mean(z64), z32 - mean(z32), z_or - mean(z_or)
     e64, e32 = rel(z64, z_or), rel(z32, z_or)
-    print(f"N={N} levels {orders} rho {np.round(rho, 3)}: V-cycle fp64 {e64:.2e}, fp32 {e32:.2e}")
+    print(f"N={N} {smoother} levels {orders} rho {np.round(rho, 3)}: V-cycle fp64 {e64:.2e}, "
+          f"fp32 {e32:.2e}")
     assert e64 <= 1e-9
     assert e32 <= 2e-4
     return M, pmg, rho
@@ -207,3 +208,110 @@ def test_pmg_errors():
             M.setup_pmg(**bad)
     with pytest.raises(sem.SemError, match="EINVAL"):
         sem.solve(M, b, mode="mixed_ir", precond="pmg", precond_prec="fp64")
+
+
+# ------------------------------------------------------------ Schwarz smoothing
+
+def test_schwarz_vcycle_matches_oracle_dirichlet_cube():
+    m, _ = config_mesh(1, N=7)
+    _vcycle_case(m, 7, smoother="schwarz")
+
+
+def test_schwarz_vcycle_matches_oracle_neumann_clustered_box():
+    m, _ = config_mesh(5, shape=(4, 4, 4))
+    _vcycle_case(m, 9, seed=2, smoother="schwarz")
+
+
+def test_schwarz_vcycle_periodic_deformed_box_variable_k():
+    m = box_mesh(6, (5, 3, 4), (2.0, 1.0, 1.0), periodic=(True, True, False), dirichlet="z",
+                 z_ratio=4.0, deform=dict(a=0.15, seed=1, kind="periodic"))
+    k = np.exp(0.3 * np.random.default_rng(9).standard_normal((m.E, m.P)))
+    _vcycle_case(m, 6, k=k, h2=0.5, seed=4, smoother="schwarz")
+
+
+def test_schwarz_bound_brackets_the_largest_eigenvalue():
+    """lambda_max of the Schwarz-preconditioned operator on each smoothing
+    level: the GPU's 20-step Lanczos estimate against a dense eigensolver."""
+    m = box_mesh(4, (3, 3, 3), (1.0, 1.5, 1.0), dirichlet="all", jitter=0.05,
+                 deform=dict(a=0.15, seed=3, kind="walls"))
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, 4)
+    M.setup_pmg(smoother="schwarz")
+    sem.pmg_apply(M, dev(np.zeros((m.E, m.P))))
+    orders, rho = M.pmg_info()
+    pmg = PMG(m.xyz, m.gid, m.dirichlet, 4, coarse="exact", smoother="schwarz")
+    for l in range(len(orders) - 1):
+        P = pmg.levels[l]
+        A = oracle.explicit_matrix(P.G, P.B, P.N, P.num).toarray()
+        n = A.shape[0]
+        Smat = np.stack([pmg.S[l](np.eye(n)[i]) for i in range(n)], 1)
+        true = np.max(np.linalg.eigvals(Smat @ A).real)
+        est = rho[l] / 1.1
+        print(f"level {l} (N={orders[l]}): Schwarz bound {est:.4f}, true {true:.4f}")
+        assert 0.95 * true <= est <= true * (1 + 1e-8)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_schwarz_pmg_fcg_matches_oracle(prec):
+    m, fld = config_mesh(3, N=9)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, 9)
+    M.setup_pmg(smoother="schwarz")
+    f = fld["f"] * 3 * np.pi ** 2
+    bL = sem.gs(M, sem.mass(M, dev(f)))
+    x, st = sem.solve(M, bL, precond="pmg", precond_prec=prec, rtol=1e-10)
+    _, rho = M.pmg_info()
+    pmg = PMG(m.xyz, m.gid, m.dirichlet, 9, rho=rho, smoother="schwarz")
+    P = pmg.levels[0]
+    b_or = P.rhs_from_source(f)
+    ref = pmg.solve(b_or, rtol=1e-10)
+    jac = P.solve(b_or, rtol=1e-12)
+    res, xf = _true_rel_residual(P, x.cpu().numpy(), b_or)
+    print(f"Schwarz pMG {prec}: iters gpu {st['iters']} oracle {ref['iters']}, res {res:.2e}")
+    assert st["converged"] == 1 and res <= 1e-10
+    assert abs(st["iters"] - ref["iters"]) <= 2
+    assert rel(xf, jac["x"]) <= 1e-8
+
+
+def test_schwarz_pmg_neumann_and_refinement():
+    m, fld = config_mesh(5, shape=(4, 4, 4))
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    M.setup_pmg(smoother="schwarz")
+    b = dev(fld["b"])
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    b_or = P.num.from_local_consistent(fld["b"])
+    for mode in ("cg", "mixed_ir"):
+        x, st = sem.solve(M, b, mode=mode, precond="pmg", rtol=1e-10)
+        res, xf = _true_rel_residual(P, x.cpu().numpy(), b_or)
+        print(f"Schwarz pMG neumann {mode}: iters {st['iters']} outer {st['outer_iters']} "
+              f"res {res:.2e}")
+        assert st["converged"] == 1 and res <= 1.2e-10
+
+
+def test_schwarz_pmg_graph_replay_matches_eager():
+    m, fld = config_mesh(1, N=5)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    M.setup_pmg(smoother="schwarz")
+    b = sem.gs(M, sem.mass(M, dev(fld["f"])))
+    x_e, st_e = sem.solve(M, b, precond="pmg", rtol=1e-10, profile=True)
+    for rep in range(3):
+        x_g, st_g = sem.solve(M, b, precond="pmg", rtol=1e-10)
+        assert st_g["iters"] == st_e["iters"]
+        assert torch.equal(x_g, x_e), rep
+        sem.ax(M, x_g)
+        torch.cuda.synchronize()
+
+
+def test_schwarz_pmg_full_convection_box():
+    m, fld = config_mesh(2)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    M.setup_pmg(smoother="schwarz")
+    b = dev(fld["b"])
+    x, st = sem.solve(M, b, precond="pmg", rtol=1e-10)
+    w = sem.gs(M, sem.ax(M, x))
+    r = sem.mask(M, (b - w).contiguous())
+    mult = M.multiplicity()
+    bb = sem.mask(M, b.clone())
+    res = float(torch.sqrt(torch.sum(r * r / mult) / torch.sum(bb * bb / mult)))
+    print(f"convection box Schwarz pMG: {st['iters']} iterations, {st['time_ms']:.1f} ms, "
+          f"true res {res:.2e}")
+    assert st["converged"] == 1 and res <= 1.05e-10
+    assert st["iters"] <= 20
