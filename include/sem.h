@@ -278,7 +278,9 @@ typedef struct {
  * scale). */
 typedef enum { SEM_SMOOTH_JACOBI = 0, SEM_SMOOTH_SCHWARZ = 1 } sem_smoother;
 
-/* Defaults: n_levels 0, smooth_order 5, coarse_iters 20, Jacobi smoother. */
+/* Defaults: n_levels 0, smooth_order 4, coarse_iters 30, Schwarz smoother
+ * (fastest to a 1e-10 residual of the settings measured on the benchmark
+ * meshes, within 10 % on both). */
 void sem_pmg_opts_default(sem_pmg_opts* opts);
 
 /* Build (or rebuild) the hierarchy of `mesh` from the description it was set

@@ -185,8 +185,8 @@ def fixed_pcg(A, b, dinv, iters, project=None):
 class PMG:
     """The level hierarchy and the V-cycle (FP64)."""
 
-    def __init__(self, xyz, gid, dirichlet, N, k=None, h2=0.0, orders=None, smooth_order=5,
-                 coarse_iters=20, coarse="cg", rho=None, smoother="jacobi"):
+    def __init__(self, xyz, gid, dirichlet, N, k=None, h2=0.0, orders=None, smooth_order=4,
+                 coarse_iters=30, coarse="cg", rho=None, smoother="schwarz"):
         self.orders = level_orders(N) if orders is None else list(orders)
         self.m = smooth_order
         self.coarse_iters = coarse_iters

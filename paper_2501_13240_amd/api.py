@@ -95,8 +95,8 @@ class Mesh:
     def handle(self):
         return self._h
 
-    def setup_pmg(self, orders=None, smooth_order: int = 5, coarse_iters: int = 20,
-                  smoother: str = "jacobi"):
+    def setup_pmg(self, orders=None, smooth_order: int = 4, coarse_iters: int = 30,
+                  smoother: str = "schwarz"):
         """Build the p-multigrid hierarchy (sem_setup_pmg); orders default to
         N, N//2, ..., 1; smoother 'jacobi' or 'schwarz'."""
         opts = L.PmgOpts()

@@ -597,9 +597,9 @@ sem_status sem_cheb_apply(const sem_mesh* m, const double* r, double* z, const d
 void sem_pmg_opts_default(sem_pmg_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
-  o->smooth_order = 5;
-  o->coarse_iters = 20;
-  o->smoother = SEM_SMOOTH_JACOBI;
+  o->smooth_order = 4;
+  o->coarse_iters = 30;
+  o->smoother = SEM_SMOOTH_SCHWARZ;
 }
 
 sem_status sem_setup_pmg(sem_mesh* m, const sem_mesh_desc* desc, const sem_pmg_opts* opts_in,

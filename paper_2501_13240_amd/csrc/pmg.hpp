@@ -41,9 +41,9 @@ struct PmgLevel {
 
 struct Pmg {
   std::vector<PmgLevel> lv;
-  int smooth_order = 5;
-  int coarse_iters = 20;
-  int smoother = 0;  // 0 Jacobi, 1 overlapping Schwarz
+  int smooth_order = 4;
+  int coarse_iters = 30;
+  int smoother = 1;  // 0 Jacobi, 1 overlapping Schwarz
   template <typename T>
   T* vec(PmgLevel& L, int which);  // 0 r, 1 x, 2 t, 3 u, 4 w, 5 d, 6 rk, 7 q
 };

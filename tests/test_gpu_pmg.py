@@ -26,6 +26,11 @@ pytestmark = pytest.mark.gpu
 sem = pytest.importorskip("paper_2501_13240_amd")
 
 
+# cycle parameters, passed explicitly to the library and to the oracle
+_CYCLE = {"jacobi": dict(smooth_order=5, coarse_iters=20),
+          "schwarz": dict(smooth_order=4, coarse_iters=30)}
+
+
 def rel(a, b):
     return np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300)
 
@@ -36,7 +41,7 @@ def dev(a):
 
 def _vcycle_case(m, N, k=None, h2=0.0, seed=1, smoother="jacobi"):
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
-    M.setup_pmg(smoother=smoother)
+    M.setup_pmg(smoother=smoother, **_CYCLE[smoother])
     orders, _ = M.pmg_info()
     assert orders == level_orders(N)
     kd = None if k is None else dev(k)
@@ -48,7 +53,8 @@ def _vcycle_case(m, N, k=None, h2=0.0, seed=1, smoother="jacobi"):
     z64 = sem.pmg_apply(M, rL, k=kd, h2=h2, prec="fp64").cpu().numpy()
     _, rho = M.pmg_info()
     z32 = sem.pmg_apply(M, rL, k=kd, h2=h2, prec="fp32").cpu().numpy()
-    pmg = PMG(m.xyz, m.gid, m.dirichlet, N, k=k, h2=h2, rho=rho, smoother=smoother)
+    pmg = PMG(m.xyz, m.gid, m.dirichlet, N, k=k, h2=h2, rho=rho, smoother=smoother,
+              **_CYCLE[smoother])
     z_or = P0.num.to_local(pmg.vcycle(rf))
     if P0.neumann:  # the cycle's output is defined up to a constant on a singular level
         mean = lambda zl: P0.num.from_local_consistent(zl).mean()
@@ -86,11 +92,11 @@ def test_level_bounds_bracket_the_largest_eigenvalue():
     m = box_mesh(4, (3, 3, 3), (1.0, 1.5, 1.0), dirichlet="all", jitter=0.05,
                  deform=dict(a=0.15, seed=3, kind="walls"))
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, 4)
-    M.setup_pmg()
+    M.setup_pmg(smoother="jacobi", **_CYCLE["jacobi"])
     rL = dev(np.zeros((m.E, m.P)))
     sem.pmg_apply(M, rL)
     orders, rho = M.pmg_info()
-    pmg = PMG(m.xyz, m.gid, m.dirichlet, 4, coarse="exact")
+    pmg = PMG(m.xyz, m.gid, m.dirichlet, 4, coarse="exact", smoother="jacobi")
     import scipy.linalg as sla
     for l, P in enumerate(pmg.levels):
         A = oracle.explicit_matrix(P.G, P.B, P.N, P.num).toarray()
@@ -112,11 +118,12 @@ def _true_rel_residual(P, x_local, b_free):
 def test_pmg_fcg_matches_oracle(cfg, N, prec):
     m, fld = config_mesh(cfg, N=N)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    M.setup_pmg(smoother="jacobi", **_CYCLE["jacobi"])
     f = fld["f"] * 3 * np.pi ** 2
     bL = sem.gs(M, sem.mass(M, dev(f)))
     x, st = sem.solve(M, bL, precond="pmg", precond_prec=prec, rtol=1e-10)
     _, rho = M.pmg_info()
-    pmg = PMG(m.xyz, m.gid, m.dirichlet, N, rho=rho)
+    pmg = PMG(m.xyz, m.gid, m.dirichlet, N, rho=rho, smoother="jacobi", **_CYCLE["jacobi"])
     P = pmg.levels[0]
     b_or = P.rhs_from_source(f)
     ref = pmg.solve(b_or, rtol=1e-10)
@@ -145,10 +152,11 @@ def test_pmg_inside_mixed_refinement():
 def test_pmg_fcg_neumann_clustered_box():
     m, fld = config_mesh(5, shape=(4, 4, 4))
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    M.setup_pmg(smoother="jacobi", **_CYCLE["jacobi"])
     b = dev(fld["b"])
     x, st = sem.solve(M, b, precond="pmg", rtol=1e-10)
     _, rho = M.pmg_info()
-    pmg = PMG(m.xyz, m.gid, m.dirichlet, m.N, rho=rho)
+    pmg = PMG(m.xyz, m.gid, m.dirichlet, m.N, rho=rho, smoother="jacobi", **_CYCLE["jacobi"])
     P = pmg.levels[0]
     b_or = P.num.from_local_consistent(fld["b"])
     ref = pmg.solve(b_or, rtol=1e-10)
@@ -163,6 +171,7 @@ def test_pmg_fcg_neumann_clustered_box():
 def test_pmg_graph_replay_matches_eager():
     m, fld = config_mesh(1, N=5)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    M.setup_pmg(smoother="jacobi", **_CYCLE["jacobi"])
     b = sem.gs(M, sem.mass(M, dev(fld["f"])))
     x_e, st_e = sem.solve(M, b, precond="pmg", rtol=1e-10, profile=True)
     for rep in range(3):
@@ -179,6 +188,7 @@ def test_pmg_full_convection_box_converges():
     in a small fraction of the Jacobi-PCG iterations."""
     m, fld = config_mesh(2)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    M.setup_pmg(smoother="jacobi", **_CYCLE["jacobi"])
     b = dev(fld["b"])
     x, st = sem.solve(M, b, precond="pmg", rtol=1e-8)
     w = sem.gs(M, sem.ax(M, x))
@@ -254,12 +264,12 @@ def test_schwarz_bound_brackets_the_largest_eigenvalue():
 def test_schwarz_pmg_fcg_matches_oracle(prec):
     m, fld = config_mesh(3, N=9)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, 9)
-    M.setup_pmg(smoother="schwarz")
+    M.setup_pmg(smoother="schwarz", **_CYCLE["schwarz"])
     f = fld["f"] * 3 * np.pi ** 2
     bL = sem.gs(M, sem.mass(M, dev(f)))
     x, st = sem.solve(M, bL, precond="pmg", precond_prec=prec, rtol=1e-10)
     _, rho = M.pmg_info()
-    pmg = PMG(m.xyz, m.gid, m.dirichlet, 9, rho=rho, smoother="schwarz")
+    pmg = PMG(m.xyz, m.gid, m.dirichlet, 9, rho=rho, smoother="schwarz", **_CYCLE["schwarz"])
     P = pmg.levels[0]
     b_or = P.rhs_from_source(f)
     ref = pmg.solve(b_or, rtol=1e-10)
