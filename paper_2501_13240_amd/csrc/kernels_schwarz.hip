@@ -115,11 +115,73 @@ __global__ __launch_bounds__(kFdmThreads) void fdm_kernel(const int32_t* __restr
   for (int q = t; q < P3; q += kFdmThreads) out[e * P3 + q] = sA[q];
 }
 
+// Small boxes (n <= 8, N <= 5): one wavefront per element, four elements per
+// workgroup.  A wavefront's LDS operations complete in program order, so the
+// six transforms need no workgroup barrier; a wavefront-scope fence between
+// them keeps the compiler from reordering them.
+constexpr int kFdmWaves = 4;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int n, typename T>
+__global__ __launch_bounds__(64 * kFdmWaves) void fdm_wave_kernel(
+    int64_t E, const int32_t* __restrict__ xmap, const T* __restrict__ S,
+    const T* __restrict__ lam, const T* __restrict__ r, T* __restrict__ out,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int P2 = n * n, P3 = P2 * n, NT = (P2 + 15) / 16;
+  __shared__ T sA[kFdmWaves][P3];
+  __shared__ T sB[kFdmWaves][P3];
+  __shared__ T sS[kFdmWaves][3][P2];
+  __shared__ T sL[kFdmWaves][3][n];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * kFdmWaves + w;
+  if (e >= E) return;  // the whole wavefront (no workgroup barrier follows)
+  T* A = sA[w];
+  T* B = sB[w];
+  T* Sw = &sS[w][0][0];
+  T* Lw = &sL[w][0][0];
+  for (int q = lane; q < 3 * P2; q += 64) Sw[q] = S[e * 3 * P2 + q];
+  for (int q = lane; q < 3 * n; q += 64) Lw[q] = lam[e * 3 * n + q];
+  for (int q = lane; q < P3; q += 64) {
+    const int32_t g = xmap[e * P3 + q];
+    A[q] = g >= 0 ? r[g] : T(0);
+  }
+  wave_sync();
+  for (int tile = 0; tile < NT; ++tile) fdm_tile<n, T, 0, true>(A, B, Sw, tile, lane);
+  wave_sync();
+  for (int tile = 0; tile < NT; ++tile) fdm_tile<n, T, 1, true>(B, A, Sw + P2, tile, lane);
+  wave_sync();
+  for (int tile = 0; tile < NT; ++tile) fdm_tile<n, T, 2, true>(A, B, Sw + 2 * P2, tile, lane);
+  wave_sync();
+  for (int q = lane; q < P3; q += 64) {
+    const int a = q % n, b = (q / n) % n, c = q / P2;
+    B[q] = B[q] / (Lw[a] + Lw[n + b] + Lw[2 * n + c]);
+  }
+  wave_sync();
+  for (int tile = 0; tile < NT; ++tile) fdm_tile<n, T, 2, false>(B, A, Sw + 2 * P2, tile, lane);
+  wave_sync();
+  for (int tile = 0; tile < NT; ++tile) fdm_tile<n, T, 1, false>(A, B, Sw + P2, tile, lane);
+  wave_sync();
+  for (int tile = 0; tile < NT; ++tile) fdm_tile<n, T, 0, false>(B, A, Sw, tile, lane);
+  wave_sync();
+  for (int q = lane; q < P3; q += 64) out[e * P3 + q] = A[q];
+}
+
 template <int n, typename T>
 hipError_t run_fdm(int64_t E, const int32_t* xmap, const T* S, const T* lam, const T* r, T* out,
                    const int32_t* skip, hipStream_t s) {
-  hipLaunchKernelGGL((fdm_kernel<n, T>), dim3((unsigned)E), dim3(kFdmThreads), 0, s, xmap, S, lam,
-                     r, out, skip);
+  if constexpr (n <= 8) {
+    const int64_t grid = (E + kFdmWaves - 1) / kFdmWaves;
+    hipLaunchKernelGGL((fdm_wave_kernel<n, T>), dim3((unsigned)grid), dim3(64 * kFdmWaves), 0, s,
+                       E, xmap, S, lam, r, out, skip);
+  } else {
+    hipLaunchKernelGGL((fdm_kernel<n, T>), dim3((unsigned)E), dim3(kFdmThreads), 0, s, xmap, S,
+                       lam, r, out, skip);
+  }
   return hipGetLastError();
 }
 
