@@ -24,7 +24,9 @@ definitions in order:
 * ``pmg``       the p-multigrid preconditioner with Chebyshev smoothing (the
                 default pressure preconditioner named in Sec. 2.2);
 * ``schwarz``   the overlapping Schwarz smoother with fast-diagonalisation
-                local solves that the p-multigrid cycle can accelerate.
+                local solves that the p-multigrid cycle can accelerate;
+* ``advection`` the convective term u . grad T of the Boussinesq equations
+                (Sec. 2.3), by GLL collocation or by the 3/2 Gauss rule.
 
 The paper names the method but prints none of its formulas; every function
 states the textbook definition it follows and each is pinned by a test under
@@ -40,8 +42,13 @@ from .solvers import Problem, pcg, chebyshev_apply, chebyshev1_apply, lanczos_lm
 from .pmg import PMG, coarse_mesh, interpolation_matrix, level_orders
 from .schwarz import Schwarz, extended_1d
 from .grad import solve_and_adjoint_gradient
+from .advection import convect, dealias_points, geometric_factors_q, lagrange_at
 
 __all__ = [
+    "convect",
+    "dealias_points",
+    "geometric_factors_q",
+    "lagrange_at",
     "gll_nodes_weights",
     "deriv_matrix",
     "deriv_matrix_barycentric",
