@@ -251,6 +251,48 @@ def gs_rate(sem, M, reps):
             "shared_copies": copies}
 
 
+def advection_rate(sem, M, m, reps):
+    """sem_advect on the benchmark mesh (smooth seeded velocity and scalar):
+    median of individually event-timed launches after warm-ups.  Algorithmic
+    bytes per element: u (3), f and out (P values each) plus the nine factors
+    per quadrature point (q1^3 points), in the arithmetic's width."""
+    import torch
+    from sem_inputs import random_fourier_field, velocity_field
+
+    t = time.time()
+    u64 = torch.tensor(velocity_field(m.xyz, seed=11, M=8), device="cuda")
+    f64 = torch.tensor(random_fourier_field(m.xyz, M=16, seed=7), device="cuda")
+    log(f"advection inputs in {time.time() - t:.1f}s")
+    out = {}
+    for rule in ("dealias", "collocation"):
+        t = time.time()
+        M.setup_advection(rule)
+        setup_s = time.time() - t
+        q1 = sem.advection_rule(M.N, rule)[0].size
+        for dt, width in ((torch.float64, 8), (torch.float32, 4)):
+            u, f = u64.to(dt), f64.to(dt)
+            w = torch.empty_like(f)
+            for _ in range(3):
+                sem.advect(M, u, f, rule=rule, out=w)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(reps)]
+            for e0, e1 in evs:
+                e0.record()
+                sem.advect(M, u, f, rule=rule, out=w)
+                e1.record()
+            torch.cuda.synchronize()
+            ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+            alg = float(M.E) * (5 * M.P + 9 * q1 ** 3) * width
+            name = f"{rule}_{'fp64' if width == 8 else 'fp32'}"
+            out[name] = {"us": ms * 1e3, "points_per_dir": q1,
+                         "algorithmic_bytes": alg, "gb_s": alg / ms / 1e6,
+                         "hbm_frac": alg / ms / 1e6 / PEAK_HBM_GBS,
+                         "glocal_points_s": M.E * M.P / (ms * 1e-3) / 1e9,
+                         "setup_s": setup_s}
+            log(f"  advect {name}: {ms * 1e3:.1f} us, {out[name]['gb_s']:.0f} GB/s")
+    return out
+
+
 def small_solves(sem):
     """Time to ||b - A x|| <= 1e-10 ||b|| on the 4^3-element unit cube at
     N = 7 and 9 (manufactured right-hand side): launch-bound cases, the
@@ -393,6 +435,9 @@ def main():
     gs = gs_rate(sem, M, args.ax_reps)
     log(f"sem_gs: {gs['us']:.1f} us, {gs['gb_s']:.0f} GB/s")
 
+    log("convective term (sem_advect) on the benchmark mesh ...")
+    adv = advection_rate(sem, M, m, args.ax_reps)
+
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -437,6 +482,7 @@ def main():
         "ax_us": sem_ax_ms * 1e3,
         "ax_hbm_frac": 64.0 * nL / (sem_ax_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
         "gs": gs,
+        "advection": adv,
     }
     if not args.no_extras:
         log("to 1e-10 on the benchmark mesh ...")

@@ -249,13 +249,14 @@ sem_status sem_ax_backward(const sem_mesh* mesh, const double* u, const double* 
  * position), so every level has the spectral-element operator of its order.
  * One V-cycle: pre-smoothing x = C_l(r), coarse correction
  * x += P_l V_{l+1}(P_l^T (r - A_l x)), post-smoothing x += C_l(r - A_l x),
- * with C_l the fourth-kind Chebyshev-Jacobi polynomial of order smooth_order
- * (bound 1.1 x a 20-step CG-Lanczos estimate per level, per solve), P_l the
+ * with C_l the fourth-kind Chebyshev polynomial of order smooth_order in
+ * S_l A_l (S_l the smoother below: Jacobi or overlapping Schwarz; bound
+ * 1.1 x a 20-step Lanczos estimate per level, per solve), P_l the
  * element-wise tensor-product Lagrange interpolation (averaged over the copies
  * of a fine node), P_l^T its transpose, and coarse_iters Jacobi-PCG
  * iterations from zero on the coarsest level (constant mode projected out on
- * a singular level).  Sec. 2.2 names this preconditioner family (with
- * overlapping Schwarz smoothers, not built here: the smoother is Jacobi). */
+ * a singular level).  Sec. 2.2 names this preconditioner: p-multigrid with
+ * Chebyshev-accelerated overlapping Schwarz smoothing. */
 #define SEM_PMG_MAX_LEVELS 8
 typedef struct {
   int32_t n_levels;                    /* 0: default orders; else the number of entries used */
@@ -319,6 +320,51 @@ sem_status sem_host_schwarz(int32_t N, int64_t E, const int64_t* gid, const uint
 sem_status sem_host_coarse_mesh(int32_t N, int64_t E, const int64_t* gid,
                                 const uint8_t* dirichlet, const double* xyz, int32_t Nc,
                                 int64_t* gid_c, uint8_t* dirichlet_c, double* xyz_c);
+
+/* ------------------------------------------------------ convective term
+ * The advection term u . grad f of the Boussinesq equations (Sec. 2.3: the
+ * temperature and each velocity component are advected by the velocity), in
+ * weak form per element:
+ *   C_e(u) f |_i = sum_q phi_i(x_q) w_q detJ_q u(x_q) . grad f(x_q),
+ * with u and f interpolated from the element's GLL nodes.  The paper prints
+ * no discretisation of this term; two quadratures are offered:
+ *   SEM_ADV_COLLOCATION  the GLL nodes themselves (N+1 per direction;
+ *                        aliased: the integrand has degree 3N - 1 per
+ *                        direction, the rule is exact to 2N - 1);
+ *   SEM_ADV_DEALIAS      M = floor(3(N+1)/2) Gauss-Legendre points per
+ *                        direction (over-integration by the 3/2 rule, exact
+ *                        on affine elements).
+ * The nine factors w detJ dr_a/dx_d per point are precomputed by
+ * sem_setup_advection. */
+typedef enum { SEM_ADV_COLLOCATION = 0, SEM_ADV_DEALIAS = 1 } sem_adv_rule;
+
+/* HOST-only.  The rule's points per direction (q1, nullable), points x and
+ * weights w on [-1, 1] (ascending, q1 each, nullable) and the interpolation
+ * J [q1][N+1] (row-major, nullable) from the GLL nodes to them (the identity
+ * for collocation).  1 <= N <= 10. */
+sem_status sem_advection_rule(int32_t N, int32_t rule, int32_t* q1, double* x, double* w,
+                              double* J);
+
+/* Compute the factors of `rule` for `mesh` from the description it was set
+ * up with (same N and E; HOST arrays, read during the call only).  Device
+ * memory: 9 q1^3 E values in FP64 and FP32.  Blocks.  SEM_EINVAL for a
+ * different description, an unknown rule or detJ <= 0 at a point. */
+sem_status sem_setup_advection(sem_mesh* mesh, const sem_mesh_desc* desc, int32_t rule,
+                               void* stream);
+
+/* Copy the factors of `rule` to G: DEVICE double [E][9][q1^3], slot 3 a + d
+ * holding w detJ dr_a/dx_d (a = r, s, t; d = x, y, z), points in [k][j][i]
+ * order.  Stream-ordered. */
+sem_status sem_get_advection_factors(const sem_mesh* mesh, int32_t rule, double* G,
+                                     void* stream);
+
+/* out = C_L(u) f: every element's contribution (unassembled; sem_gs sums
+ * them).  u: DEVICE [3][E][P] (x, y and z components of the velocity at the
+ * local nodes), f, out: DEVICE [E][P]; double (SEM_FP64) or float (SEM_FP32:
+ * FP32 factors and arithmetic).  out must not overlap u or f.
+ * Stream-ordered. */
+sem_status sem_advect(const sem_mesh* mesh, int32_t rule, const void* u, const void* f,
+                      void* out, sem_prec prec, void* stream);
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* sem_last_error(void);

@@ -12,6 +12,8 @@ from ._lib import LIB_PATH, load as load_library
 from .api import (
     Mesh,
     SemError,
+    advect,
+    advection_rule,
     ax,
     ax_backward,
     cheb_apply,
@@ -37,6 +39,8 @@ __all__ = [
     "load_library",
     "Mesh",
     "SemError",
+    "advect",
+    "advection_rule",
     "ax",
     "ax_backward",
     "cheb_apply",

@@ -60,6 +60,8 @@ class PmgOpts(ctypes.Structure):
                 ("coarse_iters", c_int32), ("smoother", c_int32)]
 
 
+ADV_RULE = {"collocation": 0, "dealias": 1}
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "sem_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
@@ -87,6 +89,10 @@ SIGNATURES = {
                                        c_void_p, c_void_p, c_void_p]),
     "sem_host_schwarz": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
+    "sem_advection_rule": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sem_setup_advection": (c_int32, [c_void_p, ctypes.POINTER(MeshDesc), c_int32, c_void_p]),
+    "sem_get_advection_factors": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "sem_advect": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "sem_lmax_estimate": (c_int32, [c_void_p, c_void_p, c_double, c_int32,
                                     ctypes.POINTER(c_double), c_void_p]),
     "sem_pcg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,

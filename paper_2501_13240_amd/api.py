@@ -80,6 +80,7 @@ class Mesh:
         # kept for a later sem_setup_pmg (it re-reads the description)
         self._desc_arrays = (xyz, gid, d)
         self._pmg = False
+        self._adv = set()
         desc = L.MeshDesc(self.N, self.E, _np_ptr(xyz), _np_ptr(gid), _np_ptr(d))
         h = ctypes.c_void_p()
         self.device = torch.cuda.current_device()
@@ -152,6 +153,23 @@ class Mesh:
             m = torch.ones(self.E, self.P, dtype=torch.float64, device=f"cuda:{self.device}")
             self._mult = gs(self, m)
         return self._mult
+
+    def setup_advection(self, rule: str = "dealias"):
+        """Precompute the convective term's factors for `rule` ('dealias':
+        the 3/2 Gauss rule, 'collocation': the GLL nodes)."""
+        xyz, _, _ = self._desc_arrays
+        desc = L.MeshDesc(self.N, self.E, _np_ptr(xyz), None, None)
+        _check(self._lib.sem_setup_advection(self._h, ctypes.byref(desc), L.ADV_RULE[rule],
+                                             _stream()), "sem_setup_advection")
+        self._adv.add(rule)
+
+    def advection_factors(self, rule: str = "dealias"):
+        """(E, 9, q1^3) float64: w detJ dr_a/dx_d in slot 3 a + d."""
+        q1 = advection_rule(self.N, rule)[0].size
+        G = torch.empty(self.E, 9, q1 ** 3, dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(self._lib.sem_get_advection_factors(self._h, L.ADV_RULE[rule], _ptr(G), _stream()),
+               "sem_get_advection_factors")
+        return G
 
     def geometry(self):
         G = torch.empty(self.E, 6, self.P, dtype=torch.float64, device=f"cuda:{self.device}")
@@ -232,6 +250,36 @@ def pmg_apply(mesh: Mesh, r, k=None, h2: float = 0.0, prec: str = "fp32"):
     _check(mesh._lib.sem_pmg_apply(mesh.handle, _ptr(r), _ptr(z), _ptr(k), float(h2),
                                    L.PREC[prec], _stream()), "sem_pmg_apply")
     return z
+
+
+def advection_rule(N: int, rule: str = "dealias"):
+    """(points, weights, J) of the convective term's rule (host): J
+    interpolates from the GLL nodes to the points."""
+    lib = L.load()
+    q1 = ctypes.c_int32()
+    _check(lib.sem_advection_rule(N, L.ADV_RULE[rule], ctypes.byref(q1), None, None, None),
+           "sem_advection_rule")
+    x, w, J = np.zeros(q1.value), np.zeros(q1.value), np.zeros((q1.value, N + 1))
+    _check(lib.sem_advection_rule(N, L.ADV_RULE[rule], None, _np_ptr(x), _np_ptr(w), _np_ptr(J)),
+           "sem_advection_rule")
+    return x, w, J
+
+
+def advect(mesh: Mesh, u, f, rule: str = "dealias", out=None):
+    """out = C_L(u) f, the unassembled convective term (sem_advect): u (3, E,
+    P) and f (E, P) of one dtype (float64 or float32); sets up the rule's
+    factors on first use."""
+    dt = f.dtype
+    mesh.check_local(f, dt, "f")
+    if not (u.is_cuda and u.dtype == dt and u.is_contiguous()
+            and tuple(u.shape) == (3, mesh.E, mesh.P)):
+        raise ValueError(f"u must be a contiguous CUDA {dt} tensor of shape (3, E, P)")
+    if rule not in mesh._adv:
+        mesh.setup_advection(rule)
+    w = torch.empty_like(f) if out is None else mesh.check_local(out, dt, "out")
+    _check(mesh._lib.sem_advect(mesh.handle, L.ADV_RULE[rule], _ptr(u), _ptr(f), _ptr(w),
+                                _prec_of(f), _stream()), "sem_advect")
+    return w
 
 
 def host_coarse_mesh(N: int, gid: np.ndarray, dirichlet, xyz, Nc: int):

@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "advection.hpp"
 #include "common.hpp"
 #include "pmg.hpp"
 #include "solver.hpp"
@@ -340,6 +341,8 @@ static sem_status check_mesh(const sem_mesh* m) {
 sem_mesh::~sem_mesh() {
   pmg_destroy(pmg);
   delete work;
+  delete adv[0];
+  delete adv[1];
 }
 
 using namespace sem;
@@ -741,6 +744,110 @@ sem_status sem_host_coarse_mesh(int32_t N, int64_t E, const int64_t* gid,
   if ((xyz == nullptr) != (xyz_c == nullptr))
     return fail(SEM_EINVAL, "xyz and xyz_c must both be given or both be NULL");
   return host_coarse_mesh(N, E, gid, dirichlet, xyz, Nc, gid_c, dirichlet_c, xyz_c);
+}
+
+sem_status sem_advection_rule(int32_t N, int32_t rule, int32_t* q1, double* x, double* w,
+                              double* J) {
+  if (sem_status st = host_adv_rule(N, rule, x, w, J)) return st;
+  if (q1) *q1 = adv_points(N, rule);
+  return SEM_OK;
+}
+
+sem_status sem_setup_advection(sem_mesh* m, const sem_mesh_desc* desc, int32_t rule,
+                               void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!desc || !desc->xyz) return fail(SEM_EINVAL, "desc and xyz are required");
+  if (desc->N != m->N || desc->E != m->E)
+    return fail(SEM_EINVAL, "the description differs from the one the mesh was set up with");
+  if (rule != SEM_ADV_COLLOCATION && rule != SEM_ADV_DEALIAS)
+    return fail(SEM_EINVAL, "unknown quadrature rule");
+  for (int64_t a = 0; a < 3 * m->nL; ++a)
+    if (!std::isfinite(desc->xyz[a])) return fail(SEM_EINVAL, "xyz holds a non-finite value");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = m->n1, q1 = adv_points(m->N, rule);
+  const int64_t Q = (int64_t)q1 * q1 * q1;
+  std::vector<double> x(q1), w(q1), J((size_t)q1 * n);
+  sem_status st;
+  if ((st = host_adv_rule(m->N, rule, x.data(), w.data(), J.data()))) return st;
+  // J, JD = J D, J^T
+  std::vector<double> mats((size_t)3 * q1 * n);
+  double* JD = mats.data() + q1 * n;
+  double* JT = JD + q1 * n;
+  for (int i = 0; i < q1; ++i)
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int l = 0; l < n; ++l) acc += J[i * n + l] * m->h_D[l * n + j];
+      mats[i * n + j] = J[i * n + j];
+      JD[i * n + j] = acc;
+      JT[j * q1 + i] = J[i * n + j];
+    }
+  std::vector<float> mats32(mats.begin(), mats.end());
+  std::unique_ptr<AdvRule> R(new AdvRule());
+  R->q1 = q1;
+  if ((st = upload(R->mats64, mats, s)) || (st = upload(R->mats32, mats32, s)) ||
+      (st = R->G64.ensure((size_t)m->E * 9 * Q * sizeof(double))) ||
+      (st = R->G32.ensure((size_t)m->E * 9 * Q * sizeof(float))))
+    return st;
+  DevBuf dxyz, dw, dbad;
+  if ((st = dxyz.ensure((size_t)3 * m->nL * sizeof(double))) || (st = upload(dw, w, s)) ||
+      (st = dbad.ensure(sizeof(int))))
+    return st;
+  SEM_HIP(hipMemcpyAsync(dxyz.p, desc->xyz, (size_t)3 * m->nL * sizeof(double),
+                         hipMemcpyHostToDevice, s));
+  SEM_HIP(launch_fill<int>(dbad.as<int>(), 1, 0, s));
+  SEM_HIP(launch_adv_geometry(m, q1, R->mats64.as<double>(), dw.as<double>(),
+                              dxyz.as<double>(), R->G64.as<double>(), R->G32.as<float>(),
+                              dbad.as<int>(), s));
+  int bad = 0;
+  SEM_HIP(hipMemcpyAsync(&bad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  if (bad > 0)
+    return fail(SEM_EINVAL, "element map is not orientation-preserving (detJ <= 0) at " +
+                                std::to_string(bad) + " quadrature points");
+  delete m->adv[rule];
+  m->adv[rule] = R.release();
+  return SEM_OK;
+}
+
+sem_status sem_get_advection_factors(const sem_mesh* m, int32_t rule, double* G, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (rule != SEM_ADV_COLLOCATION && rule != SEM_ADV_DEALIAS)
+    return fail(SEM_EINVAL, "unknown quadrature rule");
+  const AdvRule* R = m->adv[rule];
+  if (!R) return fail(SEM_EINVAL, "rule not set up: call sem_setup_advection first");
+  if (!G) return fail(SEM_EINVAL, "G must not be NULL");
+  SEM_HIP(hipMemcpyAsync(G, R->G64.p, R->G64.bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char *pa = (const char*)a, *pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+sem_status sem_advect(const sem_mesh* m, int32_t rule, const void* u, const void* f, void* out,
+                      sem_prec prec, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (rule != SEM_ADV_COLLOCATION && rule != SEM_ADV_DEALIAS)
+    return fail(SEM_EINVAL, "unknown quadrature rule");
+  const AdvRule* R = m->adv[rule];
+  if (!R) return fail(SEM_EINVAL, "rule not set up: call sem_setup_advection first");
+  if (!u || !f || !out) return fail(SEM_EINVAL, "u, f and out must not be NULL");
+  if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_EINVAL, "prec must be FP64 or FP32");
+  const size_t sz = prec == SEM_FP64 ? sizeof(double) : sizeof(float), nb = (size_t)m->nL * sz;
+  if (overlaps(out, nb, u, 3 * nb) || overlaps(out, nb, f, nb))
+    return fail(SEM_EINVAL, "out must not overlap u or f");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == SEM_FP64)
+    e = launch_advect<double>(m, rule, R->mats64.as<double>(), m->D64.as<double>(),
+                              R->G64.as<double>(), (const double*)u, (const double*)f,
+                              (double*)out, s);
+  else
+    e = launch_advect<float>(m, rule, R->mats32.as<float>(), m->D32.as<float>(),
+                             R->G32.as<float>(), (const float*)u, (const float*)f, (float*)out, s);
+  if (e != hipSuccess) return hip_fail(e, "advect");
+  return SEM_OK;
 }
 
 sem_status sem_lmax_estimate(const sem_mesh* m, const double* k, double h2, int32_t steps,

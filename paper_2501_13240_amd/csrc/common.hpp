@@ -156,6 +156,7 @@ __device__ __forceinline__ Tacc segment_sum(const int32_t* __restrict__ perm,
 // ------------------------------------------------------------- the mesh
 struct SolveWork;
 struct Pmg;
+struct AdvRule;
 
 }  // namespace sem
 
@@ -177,6 +178,7 @@ struct sem_mesh {
   double cached_lmax = 0.0;
   sem::SolveWork* work = nullptr;
   sem::Pmg* pmg = nullptr;              // p-multigrid hierarchy (sem_setup_pmg)
+  sem::AdvRule* adv[2] = {nullptr, nullptr};  // convective-term rules (sem_setup_advection)
   ~sem_mesh();
 };
 

@@ -1,0 +1,402 @@
+// Convective term C_e(u) f on every element (the advection of Sec. 2.3).
+//
+// Over-integrated rule (M = floor(3(N+1)/2) Gauss points per direction), one
+// element per workgroup of four wavefronts:
+//   1. each velocity component u_d is interpolated to the M^3 points,
+//      (J x J x J) u_d, and folded into V_a = sum_d G_ad u_d (a = r, s, t);
+//      the nine factors G_ad = w detJ dr_a/dx_d are streamed from HBM once;
+//   2. the reference derivatives of f at the points, (J x J x JD) f,
+//      (J x JD x J) f and (JD x J x J) f with JD = J D, give
+//      c = sum_a V_a df/dr_a;
+//   3. the test functions project back: out = (J^T x J^T x J^T) c.
+// Every 1-D interpolation is a batch of 16-column tiles of a 16x16x4 MFMA
+// product (the M x (N+1) matrix J fits one tile, N <= 10), staged through
+// LDS; the last interpolation stage (along t) keeps its tile in registers,
+// where V and c are formed, so no M^3 array of u or of the derivatives is
+// ever stored.  The streaming of the factors (9 M^3 values against 5 (N+1)^3
+// of fields) bounds the kernel by HBM bandwidth.
+//
+// Collocation (the GLL nodes themselves): one thread per node, derivative
+// sums over LDS.
+#include "advection.hpp"
+#include "mfma16.hpp"
+
+namespace sem {
+namespace {
+
+// dst = A src along direction DIR of an [S2][S1][S0] array (index 0
+// fastest); the extent along DIR changes from NI to NO.  A is NO x NI,
+// passed as this lane's fragments a[s] = A[lane % 16][4 s + lane / 16].
+// The columns of the product are the points of the other two directions,
+// in storage order.
+template <typename T, int S2, int S1, int S0, int NO, int DIR>
+struct Ct {
+  typedef typename Mm<T>::V V;
+  static constexpr int NI = DIR == 0 ? S0 : DIR == 1 ? S1 : S2;
+  static constexpr int NC = S2 * S1 * S0 / NI;
+  static constexpr int NT = (NC + 15) / 16;
+  static constexpr int KS = (NI + 3) / 4;
+  static_assert(NI <= 16 && NO <= 16, "one MFMA tile per matrix");
+  // address of (column c, index l along DIR) with extent L along DIR
+  template <int L>
+  static __device__ __forceinline__ int addr(int c, int l) {
+    if constexpr (DIR == 0) return c * L + l;
+    else if constexpr (DIR == 1) return (c / S0) * (L * S0) + l * S0 + c % S0;
+    else return l * (S1 * S0) + c;
+  }
+  static __device__ __forceinline__ V tile(const T* __restrict__ src, const T* a, int t,
+                                           int lane) {
+    const int col = t * 16 + (lane & 15);
+    const bool cv = col < NC;
+    const int kk = lane >> 4;
+    V acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int l = 4 * s + kk;
+      const T b = (cv && l < NI) ? src[addr<NI>(cv ? col : 0, l)] : T(0);
+      acc = Mm<T>::mma(a[s], b, acc);
+    }
+    return acc;
+  }
+  static __device__ __forceinline__ void store(T* __restrict__ dst, V acc, int t, int lane) {
+    const int col = t * 16 + (lane & 15);
+    if (col >= NC) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = Mm<T>::row(lane, r);
+      if (row < NO) dst[addr<NO>(col, row)] = acc[r];
+    }
+  }
+};
+
+// this lane's fragments of the NO x NI row-major matrix A
+template <typename T, int NO, int NI>
+__device__ __forceinline__ void fragments(const T* __restrict__ A, T* a, int lane) {
+  constexpr int KS = (NI + 3) / 4;
+  const int row = lane & 15;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int l = 4 * s + (lane >> 4);
+    a[s] = (row < NO && l < NI) ? A[row * NI + l] : T(0);
+  }
+}
+
+constexpr int kAdvWaves = 4;
+constexpr int kAdvThreads = 64 * kAdvWaves;
+
+// The interpolation stages of an order-N element to M points per direction.
+template <int N, int M, typename T>
+struct Stages {
+  static constexpr int n = N + 1, P = n * n * n, Q = M * M * M;
+  typedef Ct<T, n, n, n, M, 0> I0;  // (n,n,n) -> (n,n,M)
+  typedef Ct<T, n, n, M, M, 1> I1;  // (n,n,M) -> (n,M,M)
+  typedef Ct<T, n, M, M, M, 2> I2;  // (n,M,M) -> (M,M,M)
+  typedef Ct<T, M, M, M, n, 2> B2;  // (M,M,M) -> (n,M,M)
+  typedef Ct<T, n, M, M, n, 1> B1;  // (n,M,M) -> (n,n,M)
+  typedef Ct<T, n, n, M, n, 0> B0;  // (n,n,M) -> (n,n,n)
+  static constexpr int KN = I0::KS, KM = B2::KS;
+  static constexpr int TPW = (I2::NT + kAdvWaves - 1) / kAdvWaves;  // last-stage tiles per wave
+  // LDS: the input block and the two first-stage outputs (later the M^3
+  // array c and the (n,n,M) back-projection stage), and one (n,M,M) array
+  static constexpr int IX = P + 2 * n * n * M;
+  static constexpr int YS = n * M * M;
+  static_assert(Q <= IX && P <= YS, "LDS regions");
+};
+
+template <int N, typename T>
+__global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
+    const T* __restrict__ mats, const T* __restrict__ G, const T* __restrict__ u, int64_t ustride,
+    const T* __restrict__ f, T* __restrict__ out) {
+  constexpr int M = (3 * (N + 1)) / 2;
+  typedef Stages<N, M, T> S;
+  typedef typename Mm<T>::V V;
+  constexpr int n = S::n, P = S::P, Q = S::Q, TPW = S::TPW;
+  __shared__ T sIX[S::IX];
+  __shared__ T sY[S::YS];
+  T* sIn = sIX;
+  T* sX0 = sIX + P;
+  T* sX1 = sX0 + n * n * M;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t e = blockIdx.x;
+  T aJ[S::KN], aJD[S::KN], aJT[S::KM];
+  fragments<T, M, n>(mats, aJ, lane);
+  fragments<T, M, n>(mats + M * n, aJD, lane);
+  fragments<T, n, M>(mats + 2 * M * n, aJT, lane);
+  const T* Ge = G + e * 9 * Q;
+
+  // 1. V_a = sum_d G_ad (J x J x J) u_d, held in the last stage's tiles
+  V Va[TPW][3];
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Va[ti][a] = V{T(0), T(0), T(0), T(0)};
+  for (int d = 0; d < 3; ++d) {
+    const T* ud = u + d * ustride + e * P;
+    for (int q = threadIdx.x; q < P; q += kAdvThreads) sIn[q] = ud[q];
+    __syncthreads();
+    for (int t = wv; t < S::I0::NT; t += kAdvWaves)
+      S::I0::store(sX0, S::I0::tile(sIn, aJ, t, lane), t, lane);
+    __syncthreads();
+    for (int t = wv; t < S::I1::NT; t += kAdvWaves)
+      S::I1::store(sY, S::I1::tile(sX0, aJ, t, lane), t, lane);
+    __syncthreads();
+#pragma unroll
+    for (int ti = 0; ti < TPW; ++ti) {
+      const int t = wv + ti * kAdvWaves;
+      if (t < S::I2::NT) {
+        const V ui = S::I2::tile(sY, aJ, t, lane);
+        const int col = t * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = Mm<T>::row(lane, r);
+          if (row < M && col < M * M) {
+            const int pt = row * M * M + col;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Va[ti][a][r] += Ge[(3 * a + d) * Q + pt] * ui[r];
+          }
+        }
+      }
+    }
+  }
+
+  // 2. c = sum_a V_a df/dr_a
+  for (int q = threadIdx.x; q < P; q += kAdvThreads) sIn[q] = f[e * P + q];
+  __syncthreads();
+  for (int t = wv; t < S::I0::NT; t += kAdvWaves) {
+    S::I0::store(sX0, S::I0::tile(sIn, aJ, t, lane), t, lane);
+    S::I0::store(sX1, S::I0::tile(sIn, aJD, t, lane), t, lane);
+  }
+  __syncthreads();
+  V c[TPW];
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti) c[ti] = V{T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // r: (J x J x JD), s: (J x JD x J), t: (JD x J x J)
+    const T* src = a == 0 ? sX1 : sX0;
+    const T* a1 = a == 1 ? aJD : aJ;
+    const T* a2 = a == 2 ? aJD : aJ;
+    for (int t = wv; t < S::I1::NT; t += kAdvWaves)
+      S::I1::store(sY, S::I1::tile(src, a1, t, lane), t, lane);
+    __syncthreads();
+#pragma unroll
+    for (int ti = 0; ti < TPW; ++ti) {
+      const int t = wv + ti * kAdvWaves;
+      if (t < S::I2::NT) {
+        const V fa = S::I2::tile(sY, a2, t, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[ti][r] += Va[ti][a][r] * fa[r];
+      }
+    }
+    __syncthreads();
+  }
+  // c into the first region (its input and first-stage arrays are dead)
+  T* sC = sIX;
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti) {
+    const int t = wv + ti * kAdvWaves;
+    if (t < S::I2::NT) S::I2::store(sC, c[ti], t, lane);
+  }
+  __syncthreads();
+
+  // 3. out = (J^T x J^T x J^T) c
+  for (int t = wv; t < S::B2::NT; t += kAdvWaves)
+    S::B2::store(sY, S::B2::tile(sC, aJT, t, lane), t, lane);
+  __syncthreads();
+  for (int t = wv; t < S::B1::NT; t += kAdvWaves)
+    S::B1::store(sIX, S::B1::tile(sY, aJT, t, lane), t, lane);
+  __syncthreads();
+  for (int t = wv; t < S::B0::NT; t += kAdvWaves)
+    S::B0::store(out + e * P, S::B0::tile(sIX, aJT, t, lane), t, lane);
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(kAdvThreads) void adv_colloc_kernel(
+    const T* __restrict__ D, const T* __restrict__ G, const T* __restrict__ u, int64_t ustride,
+    const T* __restrict__ f, T* __restrict__ out) {
+  constexpr int n = N + 1, P = n * n * n;
+  __shared__ T sF[P];
+  __shared__ T sD[n * n];
+  const int64_t e = blockIdx.x;
+  for (int q = threadIdx.x; q < P; q += kAdvThreads) sF[q] = f[e * P + q];
+  for (int q = threadIdx.x; q < n * n; q += kAdvThreads) sD[q] = D[q];
+  __syncthreads();
+  const T* Ge = G + e * 9 * P;
+  for (int q = threadIdx.x; q < P; q += kAdvThreads) {
+    const int i = q % n, j = (q / n) % n, k = q / (n * n);
+    T fr = T(0), fs = T(0), ft = T(0);
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      fr += sD[i * n + l] * sF[(k * n + j) * n + l];
+      fs += sD[j * n + l] * sF[(k * n + l) * n + i];
+      ft += sD[k * n + l] * sF[(l * n + j) * n + i];
+    }
+    T c = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      c += u[d * ustride + e * P + q] *
+           (Ge[d * P + q] * fr + Ge[(3 + d) * P + q] * fs + Ge[(6 + d) * P + q] * ft);
+    out[e * P + q] = c;
+  }
+}
+
+// dX[e][3 c + a] = dx_c/dr_a at the rule's points: the reference gradient of
+// each coordinate, by the same stages as f in the dealiased kernel
+template <int N, int M>
+__global__ __launch_bounds__(kAdvThreads) void adv_metric_kernel(const double* __restrict__ mats,
+                                                                 const double* __restrict__ xyz,
+                                                                 double* __restrict__ dX) {
+  typedef Stages<N, M, double> S;
+  constexpr int n = S::n, P = S::P, Q = S::Q;
+  __shared__ double sIX[S::IX];
+  __shared__ double sY[S::YS];
+  double* sIn = sIX;
+  double* sX0 = sIX + P;
+  double* sX1 = sX0 + n * n * M;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t e = blockIdx.x;
+  double aJ[S::KN], aJD[S::KN];
+  fragments<double, M, n>(mats, aJ, lane);
+  fragments<double, M, n>(mats + M * n, aJD, lane);
+  for (int cc = 0; cc < 3; ++cc) {
+    for (int q = threadIdx.x; q < P; q += kAdvThreads) sIn[q] = xyz[(e * P + q) * 3 + cc];
+    __syncthreads();
+    for (int t = wv; t < S::I0::NT; t += kAdvWaves) {
+      S::I0::store(sX0, S::I0::tile(sIn, aJ, t, lane), t, lane);
+      S::I0::store(sX1, S::I0::tile(sIn, aJD, t, lane), t, lane);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double* src = a == 0 ? sX1 : sX0;
+      const double* a1 = a == 1 ? aJD : aJ;
+      const double* a2 = a == 2 ? aJD : aJ;
+      for (int t = wv; t < S::I1::NT; t += kAdvWaves)
+        S::I1::store(sY, S::I1::tile(src, a1, t, lane), t, lane);
+      __syncthreads();
+      double* dst = dX + (e * 9 + 3 * cc + a) * Q;
+      for (int t = wv; t < S::I2::NT; t += kAdvWaves)
+        S::I2::store(dst, S::I2::tile(sY, a2, t, lane), t, lane);
+      __syncthreads();
+    }
+  }
+}
+
+// G_ad = w detJ dr_a/dx_d = w adj(dx/dr)_ad in place of dx_c/dr_a, per point
+__global__ void adv_metric_finish(int64_t E, int q1, const double* __restrict__ w1,
+                                  double* __restrict__ G, float* __restrict__ G32,
+                                  int* __restrict__ bad) {
+  const int64_t Q = (int64_t)q1 * q1 * q1;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * Q) return;
+  const int64_t e = idx / Q, q = idx % Q;
+  const int i = (int)(q % q1), j = (int)((q / q1) % q1), k = (int)(q / ((int64_t)q1 * q1));
+  double* g = G + e * 9 * Q + q;
+  double m[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) m[c][a] = g[(3 * c + a) * Q];
+  double adj[3][3];  // adj[a][d] = det * (dr_a/dx_d)
+  adj[0][0] = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+  adj[0][1] = m[0][2] * m[2][1] - m[0][1] * m[2][2];
+  adj[0][2] = m[0][1] * m[1][2] - m[0][2] * m[1][1];
+  adj[1][0] = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+  adj[1][1] = m[0][0] * m[2][2] - m[0][2] * m[2][0];
+  adj[1][2] = m[0][2] * m[1][0] - m[0][0] * m[1][2];
+  adj[2][0] = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+  adj[2][1] = m[0][1] * m[2][0] - m[0][0] * m[2][1];
+  adj[2][2] = m[0][0] * m[1][1] - m[0][1] * m[1][0];
+  const double det = m[0][0] * adj[0][0] + m[0][1] * adj[1][0] + m[0][2] * adj[2][0];
+  if (!(det > 0.0)) atomicAdd(bad, 1);
+  const double W = w1[i] * w1[j] * w1[k];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double v = W * adj[a][d];
+      g[(3 * a + d) * Q] = v;
+      if (G32) G32[e * 9 * Q + (3 * a + d) * Q + q] = (float)v;
+    }
+}
+
+template <int N, typename T>
+hipError_t run_advect(const sem_mesh* m, int rule, const T* mats, const T* D, const T* G,
+                      const T* u, const T* f, T* out, hipStream_t s) {
+  const int64_t ustride = m->E * (int64_t)m->P;
+  if (rule == 0)
+    hipLaunchKernelGGL((adv_colloc_kernel<N, T>), dim3((unsigned)m->E), dim3(kAdvThreads), 0, s,
+                       D, G, u, ustride, f, out);
+  else
+    hipLaunchKernelGGL((adv_dealias_kernel<N, T>), dim3((unsigned)m->E), dim3(kAdvThreads), 0, s,
+                       mats, G, u, ustride, f, out);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t run_metric(const sem_mesh* m, int q1, const double* mats, const double* xyz,
+                      double* dX, hipStream_t s) {
+  constexpr int Md = (3 * (N + 1)) / 2;
+  if (q1 == N + 1)
+    hipLaunchKernelGGL((adv_metric_kernel<N, N + 1>), dim3((unsigned)m->E), dim3(kAdvThreads), 0,
+                       s, mats, xyz, dX);
+  else if (q1 == Md)
+    hipLaunchKernelGGL((adv_metric_kernel<N, Md>), dim3((unsigned)m->E), dim3(kAdvThreads), 0, s,
+                       mats, xyz, dX);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adv_geometry(const sem_mesh* m, int q1, const double* mats, const double* w1,
+                               const double* xyz, double* G, float* G32, int* bad,
+                               hipStream_t s) {
+  hipError_t err;
+  switch (m->N) {
+    case 1: err = run_metric<1>(m, q1, mats, xyz, G, s); break;
+    case 2: err = run_metric<2>(m, q1, mats, xyz, G, s); break;
+    case 3: err = run_metric<3>(m, q1, mats, xyz, G, s); break;
+    case 4: err = run_metric<4>(m, q1, mats, xyz, G, s); break;
+    case 5: err = run_metric<5>(m, q1, mats, xyz, G, s); break;
+    case 6: err = run_metric<6>(m, q1, mats, xyz, G, s); break;
+    case 7: err = run_metric<7>(m, q1, mats, xyz, G, s); break;
+    case 8: err = run_metric<8>(m, q1, mats, xyz, G, s); break;
+    case 9: err = run_metric<9>(m, q1, mats, xyz, G, s); break;
+    case 10: err = run_metric<10>(m, q1, mats, xyz, G, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (err != hipSuccess) return err;
+  const int64_t total = m->E * (int64_t)q1 * q1 * q1;
+  const int64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(adv_metric_finish, dim3((unsigned)blocks), dim3(256), 0, s, m->E, q1, w1, G,
+                     G32, bad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_advect(const sem_mesh* m, int rule, const T* mats, const T* D, const T* G,
+                         const T* u, const T* f, T* out, hipStream_t s) {
+  switch (m->N) {
+    case 1: return run_advect<1, T>(m, rule, mats, D, G, u, f, out, s);
+    case 2: return run_advect<2, T>(m, rule, mats, D, G, u, f, out, s);
+    case 3: return run_advect<3, T>(m, rule, mats, D, G, u, f, out, s);
+    case 4: return run_advect<4, T>(m, rule, mats, D, G, u, f, out, s);
+    case 5: return run_advect<5, T>(m, rule, mats, D, G, u, f, out, s);
+    case 6: return run_advect<6, T>(m, rule, mats, D, G, u, f, out, s);
+    case 7: return run_advect<7, T>(m, rule, mats, D, G, u, f, out, s);
+    case 8: return run_advect<8, T>(m, rule, mats, D, G, u, f, out, s);
+    case 9: return run_advect<9, T>(m, rule, mats, D, G, u, f, out, s);
+    case 10: return run_advect<10, T>(m, rule, mats, D, G, u, f, out, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_advect<double>(const sem_mesh*, int, const double*, const double*,
+                                          const double*, const double*, const double*, double*,
+                                          hipStream_t);
+template hipError_t launch_advect<float>(const sem_mesh*, int, const float*, const float*,
+                                         const float*, const float*, const float*, float*,
+                                         hipStream_t);
+
+}  // namespace sem

@@ -8,35 +8,11 @@
 // free node completes z = sum_e R_e^T A~_e^{-1} R_e r.  Each 1-D transform of
 // the box is a batch of 16-column tiles C = M X on the matrix cores (16x16x4
 // MFMA in FP64 or FP32) with M = S or S^T of this element, read from LDS.
+#include "mfma16.hpp"
 #include "schwarz.hpp"
 
 namespace sem {
 namespace {
-
-typedef double v4d_t __attribute__((ext_vector_type(4)));
-typedef float v4f_t __attribute__((ext_vector_type(4)));
-
-// 16x16x4 MFMA: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; result
-// (i, j) in lane 16 (i % 4) + j, register i / 4 (FP64) or lane 16 (i / 4) + j,
-// register i % 4 (FP32)
-template <typename T>
-struct Mm;
-template <>
-struct Mm<double> {
-  typedef v4d_t V;
-  static __device__ __forceinline__ V mma(double a, double b, V c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-template <>
-struct Mm<float> {
-  typedef v4f_t V;
-  static __device__ __forceinline__ V mma(float a, float b, V c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
 
 // one 16-column tile of dst = M src along direction DIR of an n^3 box
 // ([k][j][i]); M = S^T (TRANS) or S, S row-major n x n in LDS

@@ -23,10 +23,12 @@ from .fields import (
     random_fourier_field,
     random_local_normal,
     unique_dirichlet_flags,
+    velocity_field,
 )
 from .configs import config_mesh, CONFIGS
 
 __all__ = [
+    "velocity_field",
     "BoxMesh",
     "box_mesh",
     "reference_node_placement",

@@ -50,6 +50,12 @@ def random_fourier_field(xyz: np.ndarray, M: int = 64, ell: float = 0.2, seed: i
     return g.reshape(shp)
 
 
+def velocity_field(xyz: np.ndarray, seed: int = 11, ell: float = 0.25, M: int = 32) -> np.ndarray:
+    """(3, E, P): a smooth seeded velocity, one random Fourier field (seeds
+    seed, seed + 1, seed + 2) per component, continuous across elements."""
+    return np.stack([random_fourier_field(xyz, M=M, ell=ell, seed=seed + c) for c in range(3)])
+
+
 def random_local_normal(shape, seed: int) -> np.ndarray:
     """i.i.d. N(0,1) per local point (not copy-consistent)."""
     return np.random.default_rng(seed).standard_normal(shape)

@@ -257,3 +257,32 @@ def test_host_schwarz_matches_oracle(N, kw):
     inv = lambda S_, L_: np.einsum("edij,edj,edkj->edik", S_, 1.0 / L_, S_)
     a, b = inv(S, lam), inv(Sch.S, Sch.lam)
     assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("N", range(1, 11))
+def test_advection_rules_match_oracle_and_integrate_exactly(N):
+    from oracle.advection import quadrature
+    for rule, de in (("dealias", True), ("collocation", False)):
+        x, w, J = sem.advection_rule(N, rule)
+        xo, wo, Jo, _ = quadrature(N, de)
+        assert np.abs(x - xo).max() <= 1e-14 and np.abs(w - wo).max() <= 1e-14
+        assert np.abs(J - Jo).max() <= 1e-13
+        # exact for monomials up to degree 2 q1 - 1 (Gauss) or 2 q1 - 3 (GLL)
+        top = 2 * x.size - 1 if de else 2 * x.size - 3
+        for p in range(top + 1):
+            exact = 0.0 if p % 2 else 2.0 / (p + 1)
+            assert abs(w @ x ** p - exact) <= 1e-13
+        # J reproduces degree-N polynomials at the points
+        xg, _, _ = sem.gll(N)
+        c = np.random.default_rng(N).standard_normal(N + 1)
+        assert np.abs(J @ np.polyval(c, xg) - np.polyval(c, x)).max() <= 1e-12
+
+
+def test_advection_rule_rejects_bad_arguments():
+    lib = L.load()
+    assert lib.sem_advection_rule(0, 1, None, None, None, None) == L.SEM_EINVAL
+    assert lib.sem_advection_rule(11, 1, None, None, None, None) == L.SEM_EINVAL
+    assert lib.sem_advection_rule(5, 2, None, None, None, None) == L.SEM_EINVAL
+    q1 = ctypes.c_int32()
+    assert lib.sem_advection_rule(7, 1, ctypes.byref(q1), None, None, None) == L.SEM_OK
+    assert q1.value == 12
