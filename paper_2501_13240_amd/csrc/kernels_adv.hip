@@ -1,7 +1,7 @@
 // Convective term C_e(u) f on every element (the advection of Sec. 2.3).
 //
 // Over-integrated rule (M = floor(3(N+1)/2) Gauss points per direction), one
-// element per workgroup of four wavefronts:
+// element at a time per workgroup of four wavefronts:
 //   1. each velocity component u_d is interpolated to the M^3 points,
 //      (J x J x J) u_d, and folded into V_a = sum_d G_ad u_d (a = r, s, t);
 //      the nine factors G_ad = w detJ dr_a/dx_d are streamed from HBM once;
@@ -103,111 +103,148 @@ struct Stages {
   static_assert(Q <= IX && P <= YS, "LDS regions");
 };
 
+// Tiles of a stage handled by this wavefront (t = wv, wv + 4, ...), unrolled.
+#define FOR_TILES(C, ...)                                                               \
+  _Pragma("unroll") for (int ti_ = 0; ti_ < (C::NT + kAdvWaves - 1) / kAdvWaves; ++ti_) { \
+    const int t = wv + ti_ * kAdvWaves;                                                 \
+    if (t < C::NT) { __VA_ARGS__; }                                                     \
+  }
+
+// Persistent: workgroup b processes elements b, b + grid, ...  The factors a
+// pass consumes are requested one pass ahead (the first pass's during the
+// previous element's f pass and projection), into the registers the
+// previous pass has just consumed, so the factor stream stays in flight
+// while the matrix cores interpolate.
 template <int N, typename T>
 __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
-    const T* __restrict__ mats, const T* __restrict__ G, const T* __restrict__ u, int64_t ustride,
-    const T* __restrict__ f, T* __restrict__ out) {
+    int64_t E, const T* __restrict__ mats, const T* __restrict__ G, const T* __restrict__ u,
+    int64_t ustride, const T* __restrict__ f, T* __restrict__ out) {
   constexpr int M = (3 * (N + 1)) / 2;
   typedef Stages<N, M, T> S;
+  typedef typename S::I0 I0;
+  typedef typename S::I1 I1;
+  typedef typename S::I2 I2;
+  typedef typename S::B2 B2;
+  typedef typename S::B1 B1;
+  typedef typename S::B0 B0;
   typedef typename Mm<T>::V V;
   constexpr int n = S::n, P = S::P, Q = S::Q, TPW = S::TPW;
-  __shared__ T sIX[S::IX];
+  // the four input blocks and the first-stage outputs; later c and the
+  // (n,n,M) projection stage
+  constexpr int R0 = 4 * P + 2 * n * n * M;
+  static_assert(Q <= R0, "c fits the first region");
+  __shared__ T sR[R0];
   __shared__ T sY[S::YS];
-  T* sIn = sIX;
-  T* sX0 = sIX + P;
+  T* sIn = sR;  // u_x, u_y, u_z, f
+  T* sX0 = sR + 4 * P;
   T* sX1 = sX0 + n * n * M;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t e = blockIdx.x;
   T aJ[S::KN], aJD[S::KN], aJT[S::KM];
   fragments<T, M, n>(mats, aJ, lane);
   fragments<T, M, n>(mats + M * n, aJD, lane);
   fragments<T, n, M>(mats + 2 * M * n, aJT, lane);
-  const T* Ge = G + e * 9 * Q;
-
-  // 1. V_a = sum_d G_ad (J x J x J) u_d, held in the last stage's tiles
-  V Va[TPW][3];
-#pragma unroll
-  for (int ti = 0; ti < TPW; ++ti)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) Va[ti][a] = V{T(0), T(0), T(0), T(0)};
-  for (int d = 0; d < 3; ++d) {
-    const T* ud = u + d * ustride + e * P;
-    for (int q = threadIdx.x; q < P; q += kAdvThreads) sIn[q] = ud[q];
-    __syncthreads();
-    for (int t = wv; t < S::I0::NT; t += kAdvWaves)
-      S::I0::store(sX0, S::I0::tile(sIn, aJ, t, lane), t, lane);
-    __syncthreads();
-    for (int t = wv; t < S::I1::NT; t += kAdvWaves)
-      S::I1::store(sY, S::I1::tile(sX0, aJ, t, lane), t, lane);
-    __syncthreads();
-#pragma unroll
-    for (int ti = 0; ti < TPW; ++ti) {
-      const int t = wv + ti * kAdvWaves;
-      if (t < S::I2::NT) {
-        const V ui = S::I2::tile(sY, aJ, t, lane);
-        const int col = t * 16 + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = Mm<T>::row(lane, r);
-          if (row < M && col < M * M) {
-            const int pt = row * M * M + col;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) Va[ti][a][r] += Ge[(3 * a + d) * Q + pt] * ui[r];
-          }
-        }
-      }
-    }
-  }
-
-  // 2. c = sum_a V_a df/dr_a
-  for (int q = threadIdx.x; q < P; q += kAdvThreads) sIn[q] = f[e * P + q];
-  __syncthreads();
-  for (int t = wv; t < S::I0::NT; t += kAdvWaves) {
-    S::I0::store(sX0, S::I0::tile(sIn, aJ, t, lane), t, lane);
-    S::I0::store(sX1, S::I0::tile(sIn, aJD, t, lane), t, lane);
-  }
-  __syncthreads();
-  V c[TPW];
-#pragma unroll
-  for (int ti = 0; ti < TPW; ++ti) c[ti] = V{T(0), T(0), T(0), T(0)};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    // r: (J x J x JD), s: (J x JD x J), t: (JD x J x J)
-    const T* src = a == 0 ? sX1 : sX0;
-    const T* a1 = a == 1 ? aJD : aJ;
-    const T* a2 = a == 2 ? aJD : aJ;
-    for (int t = wv; t < S::I1::NT; t += kAdvWaves)
-      S::I1::store(sY, S::I1::tile(src, a1, t, lane), t, lane);
-    __syncthreads();
-#pragma unroll
-    for (int ti = 0; ti < TPW; ++ti) {
-      const int t = wv + ti * kAdvWaves;
-      if (t < S::I2::NT) {
-        const V fa = S::I2::tile(sY, a2, t, lane);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) c[ti][r] += Va[ti][a][r] * fa[r];
-      }
-    }
-    __syncthreads();
-  }
-  // c into the first region (its input and first-stage arrays are dead)
-  T* sC = sIX;
+  // this lane's point in each of its last-stage tiles (-1: none)
+  int goff[TPW][4];
 #pragma unroll
   for (int ti = 0; ti < TPW; ++ti) {
     const int t = wv + ti * kAdvWaves;
-    if (t < S::I2::NT) S::I2::store(sC, c[ti], t, lane);
+    const int col = t * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = Mm<T>::row(lane, r);
+      goff[ti][r] = (t < I2::NT && row < M && col < M * M) ? row * M * M + col : -1;
+    }
   }
-  __syncthreads();
+  T g[TPW][3][4];  // G_ad of pass d at those points
+  auto fetch = [&](int64_t ee, int d) {
+    const T* Gd = G + (ee * 9 + d) * Q;
+#pragma unroll
+    for (int ti = 0; ti < TPW; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          g[ti][a][r] = goff[ti][r] >= 0 ? Gd[3 * a * Q + goff[ti][r]] : T(0);
+  };
+  int64_t e = blockIdx.x;
+  if (e < E) fetch(e, 0);
+  for (; e < E; e += gridDim.x) {
+    const int64_t en = e + gridDim.x;
+    for (int q = threadIdx.x; q < 4 * P; q += kAdvThreads) {
+      const int d = q / P, p = q - d * P;
+      sIn[q] = d < 3 ? u[d * ustride + e * P + p] : f[e * P + p];
+    }
+    __syncthreads();
 
-  // 3. out = (J^T x J^T x J^T) c
-  for (int t = wv; t < S::B2::NT; t += kAdvWaves)
-    S::B2::store(sY, S::B2::tile(sC, aJT, t, lane), t, lane);
-  __syncthreads();
-  for (int t = wv; t < S::B1::NT; t += kAdvWaves)
-    S::B1::store(sIX, S::B1::tile(sY, aJT, t, lane), t, lane);
-  __syncthreads();
-  for (int t = wv; t < S::B0::NT; t += kAdvWaves)
-    S::B0::store(out + e * P, S::B0::tile(sIX, aJT, t, lane), t, lane);
+    // 1. V_a = sum_d G_ad (J x J x J) u_d, held in the last stage's tiles
+    V Va[TPW][3];
+#pragma unroll
+    for (int ti = 0; ti < TPW; ++ti)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) Va[ti][a] = V{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      FOR_TILES(I0, I0::store(sX0, I0::tile(sIn + d * P, aJ, t, lane), t, lane));
+      __syncthreads();
+      FOR_TILES(I1, I1::store(sY, I1::tile(sX0, aJ, t, lane), t, lane));
+      __syncthreads();
+#pragma unroll
+      for (int ti = 0; ti < TPW; ++ti) {
+        const int t = wv + ti * kAdvWaves;
+        if (t < I2::NT) {
+          const V ui = I2::tile(sY, aJ, t, lane);
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Va[ti][a][r] += g[ti][a][r] * ui[r];
+        }
+      }
+      if (d < 2) fetch(e, d + 1);
+      else if (en < E) fetch(en, 0);
+    }
+
+    // 2. c = sum_a V_a df/dr_a: r (J x J x JD), s (J x JD x J), t (JD x J x J)
+    FOR_TILES(I0, I0::store(sX0, I0::tile(sIn + 3 * P, aJ, t, lane), t, lane);
+              I0::store(sX1, I0::tile(sIn + 3 * P, aJD, t, lane), t, lane));
+    __syncthreads();
+    V c[TPW];
+#pragma unroll
+    for (int ti = 0; ti < TPW; ++ti) c[ti] = V{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T* src = a == 0 ? sX1 : sX0;
+      const T* a1 = a == 1 ? aJD : aJ;
+      const T* a2 = a == 2 ? aJD : aJ;
+      FOR_TILES(I1, I1::store(sY, I1::tile(src, a1, t, lane), t, lane));
+      __syncthreads();
+#pragma unroll
+      for (int ti = 0; ti < TPW; ++ti) {
+        const int t = wv + ti * kAdvWaves;
+        if (t < I2::NT) {
+          const V fa = I2::tile(sY, a2, t, lane);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) c[ti][r] += Va[ti][a][r] * fa[r];
+        }
+      }
+      __syncthreads();
+    }
+    // c into the first region (its inputs and first-stage arrays are dead)
+    T* sC = sR;
+#pragma unroll
+    for (int ti = 0; ti < TPW; ++ti) {
+      const int t = wv + ti * kAdvWaves;
+      if (t < I2::NT) I2::store(sC, c[ti], t, lane);
+    }
+    __syncthreads();
+
+    // 3. out = (J^T x J^T x J^T) c
+    FOR_TILES(B2, B2::store(sY, B2::tile(sC, aJT, t, lane), t, lane));
+    __syncthreads();
+    FOR_TILES(B1, B1::store(sR, B1::tile(sY, aJT, t, lane), t, lane));
+    __syncthreads();
+    FOR_TILES(B0, B0::store(out + e * P, B0::tile(sR, aJT, t, lane), t, lane));
+    __syncthreads();  // the next element restages sR
+  }
 }
 
 template <int N, typename T>
@@ -324,12 +361,27 @@ template <int N, typename T>
 hipError_t run_advect(const sem_mesh* m, int rule, const T* mats, const T* D, const T* G,
                       const T* u, const T* f, T* out, hipStream_t s) {
   const int64_t ustride = m->E * (int64_t)m->P;
-  if (rule == 0)
+  if (rule == 0) {
     hipLaunchKernelGGL((adv_colloc_kernel<N, T>), dim3((unsigned)m->E), dim3(kAdvThreads), 0, s,
                        D, G, u, ustride, f, out);
-  else
-    hipLaunchKernelGGL((adv_dealias_kernel<N, T>), dim3((unsigned)m->E), dim3(kAdvThreads), 0, s,
-                       mats, G, u, ustride, f, out);
+    return hipGetLastError();
+  }
+  // persistent grid: twice the resident workgroups (measured best of 1x, 2x)
+  static const int per_cu = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, adv_dealias_kernel<N, T>, kAdvThreads,
+                                                     0) != hipSuccess || v <= 0)
+      v = 1;
+    return v;
+  }();
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  int64_t grid = 2 * (int64_t)cus * per_cu;
+  if (grid > m->E) grid = m->E;
+  hipLaunchKernelGGL((adv_dealias_kernel<N, T>), dim3((unsigned)grid), dim3(kAdvThreads), 0, s,
+                     m->E, mats, G, u, ustride, f, out);
   return hipGetLastError();
 }
 
