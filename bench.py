@@ -252,10 +252,13 @@ def gs_rate(sem, M, reps):
 
 
 def advection_rate(sem, M, m, reps):
-    """sem_advect on the benchmark mesh (smooth seeded velocity and scalar):
-    median of individually event-timed launches after warm-ups.  Algorithmic
-    bytes per element: u (3), f and out (P values each) plus the nine factors
-    per quadrature point (q1^3 points), in the arithmetic's width."""
+    """sem_advect on the benchmark mesh (smooth seeded velocity and scalar),
+    and sem_advect_fields on the four fields of a Boussinesq step (the scalar
+    and the three velocity components, advected by the velocity): median of
+    individually event-timed launches after warm-ups.  Algorithmic bytes per
+    element: u (3 P values) and the nine factors per quadrature point (9 q1^3)
+    once, plus f and out (P values each) per field, in the arithmetic's
+    width."""
     import torch
     from sem_inputs import random_fourier_field, velocity_field
 
@@ -264,6 +267,19 @@ def advection_rate(sem, M, m, reps):
     f64 = torch.tensor(random_fourier_field(m.xyz, M=16, seed=7), device="cuda")
     log(f"advection inputs in {time.time() - t:.1f}s")
     out = {}
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+
     for rule in ("dealias", "collocation"):
         t = time.time()
         M.setup_advection(rule)
@@ -271,25 +287,19 @@ def advection_rate(sem, M, m, reps):
         q1 = sem.advection_rule(M.N, rule)[0].size
         for dt, width in ((torch.float64, 8), (torch.float32, 4)):
             u, f = u64.to(dt), f64.to(dt)
-            w = torch.empty_like(f)
-            for _ in range(3):
-                sem.advect(M, u, f, rule=rule, out=w)
-            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                   for _ in range(reps)]
-            for e0, e1 in evs:
-                e0.record()
-                sem.advect(M, u, f, rule=rule, out=w)
-                e1.record()
-            torch.cuda.synchronize()
-            ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
-            alg = float(M.E) * (5 * M.P + 9 * q1 ** 3) * width
+            fields = torch.cat([f[None], u]).contiguous()
+            w, w4 = torch.empty_like(f), torch.empty_like(fields)
             name = f"{rule}_{'fp64' if width == 8 else 'fp32'}"
-            out[name] = {"us": ms * 1e3, "points_per_dir": q1,
-                         "algorithmic_bytes": alg, "gb_s": alg / ms / 1e6,
-                         "hbm_frac": alg / ms / 1e6 / PEAK_HBM_GBS,
-                         "glocal_points_s": M.E * M.P / (ms * 1e-3) / 1e9,
-                         "setup_s": setup_s}
-            log(f"  advect {name}: {ms * 1e3:.1f} us, {out[name]['gb_s']:.0f} GB/s")
+            for nf, fin, fout in ((1, f, w), (4, fields, w4)):
+                ms = timed(lambda: sem.advect(M, u, fin, rule=rule, out=fout))
+                alg = float(M.E) * (3 * M.P + 9 * q1 ** 3 + 2 * nf * M.P) * width
+                key = name if nf == 1 else name + "_4fields"
+                out[key] = {"us": ms * 1e3, "points_per_dir": q1, "fields": nf,
+                            "algorithmic_bytes": alg, "gb_s": alg / ms / 1e6,
+                            "hbm_frac": alg / ms / 1e6 / PEAK_HBM_GBS,
+                            "glocal_points_s": nf * M.E * M.P / (ms * 1e-3) / 1e9,
+                            "setup_s": setup_s}
+                log(f"  advect {key}: {ms * 1e3:.1f} us, {out[key]['gb_s']:.0f} GB/s")
     return out
 
 

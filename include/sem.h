@@ -366,6 +366,14 @@ sem_status sem_get_advection_factors(const sem_mesh* mesh, int32_t rule, double*
 sem_status sem_advect(const sem_mesh* mesh, int32_t rule, const void* u, const void* f,
                       void* out, sem_prec prec, void* stream);
 
+/* out[k] = C_L(u) f[k] for nf >= 0 fields advected by one velocity (the
+ * temperature and the three velocity components of a Boussinesq step): f,
+ * out DEVICE [nf][E][P], the rest as sem_advect.  The velocity and the
+ * factors are read once per element for all fields; each out[k] equals
+ * sem_advect's for f[k].  nf = 0 does nothing.  Stream-ordered. */
+sem_status sem_advect_fields(const sem_mesh* mesh, int32_t rule, const void* u, int32_t nf,
+                             const void* f, void* out, sem_prec prec, void* stream);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* sem_last_error(void);
 

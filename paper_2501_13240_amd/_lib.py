@@ -93,6 +93,8 @@ SIGNATURES = {
     "sem_setup_advection": (c_int32, [c_void_p, ctypes.POINTER(MeshDesc), c_int32, c_void_p]),
     "sem_get_advection_factors": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "sem_advect": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "sem_advect_fields": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
+                                    c_int32, c_void_p]),
     "sem_lmax_estimate": (c_int32, [c_void_p, c_void_p, c_double, c_int32,
                                     ctypes.POINTER(c_double), c_void_p]),
     "sem_pcg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,

@@ -266,19 +266,31 @@ def advection_rule(N: int, rule: str = "dealias"):
 
 
 def advect(mesh: Mesh, u, f, rule: str = "dealias", out=None):
-    """out = C_L(u) f, the unassembled convective term (sem_advect): u (3, E,
-    P) and f (E, P) of one dtype (float64 or float32); sets up the rule's
-    factors on first use."""
+    """out = C_L(u) f, the unassembled convective term: u (3, E, P) and f
+    (E, P) for one field (sem_advect) or (nf, E, P) for nf fields advected by
+    the same velocity (sem_advect_fields), one dtype (float64 or float32);
+    sets up the rule's factors on first use."""
     dt = f.dtype
-    mesh.check_local(f, dt, "f")
+    shape = (mesh.E, mesh.P)
+    if not (f.is_cuda and f.is_contiguous() and tuple(f.shape[-2:]) == shape
+            and f.dim() in (2, 3)):
+        raise ValueError(f"f must be a contiguous CUDA tensor of shape (E, P) or (nf, E, P)")
     if not (u.is_cuda and u.dtype == dt and u.is_contiguous()
-            and tuple(u.shape) == (3, mesh.E, mesh.P)):
+            and tuple(u.shape) == (3,) + shape):
         raise ValueError(f"u must be a contiguous CUDA {dt} tensor of shape (3, E, P)")
+    if dt not in (torch.float64, torch.float32):
+        raise TypeError("advect takes float64 or float32 data")
     if rule not in mesh._adv:
         mesh.setup_advection(rule)
-    w = torch.empty_like(f) if out is None else mesh.check_local(out, dt, "out")
-    _check(mesh._lib.sem_advect(mesh.handle, L.ADV_RULE[rule], _ptr(u), _ptr(f), _ptr(w),
-                                _prec_of(f), _stream()), "sem_advect")
+    if out is None:
+        w = torch.empty_like(f)
+    else:
+        if not (out.is_cuda and out.dtype == dt and out.is_contiguous() and out.shape == f.shape):
+            raise ValueError("out must be a contiguous CUDA tensor like f")
+        w = out
+    nf = 1 if f.dim() == 2 else f.shape[0]
+    _check(mesh._lib.sem_advect_fields(mesh.handle, L.ADV_RULE[rule], _ptr(u), nf, _ptr(f),
+                                       _ptr(w), _prec_of(f), _stream()), "sem_advect_fields")
     return w
 
 

@@ -31,11 +31,11 @@ hipError_t launch_adv_geometry(const sem_mesh* m, int q1, const double* mats, co
                                const double* xyz, double* G, float* G32, int* bad,
                                hipStream_t s);
 
-// out[e] = C_e(u) f for every element: u DEVICE [3][E][P], f and out [E][P];
-// rule 0 reads D (DEVICE [n][n]) and G [E][9][P], rule 1 mats and G
-// [E][9][q1^3]
+// out[k][e] = C_e(u) f[k] for every element and each of nf fields: u DEVICE
+// [3][E][P], f and out [nf][E][P]; rule 0 reads D (DEVICE [n][n]) and G
+// [E][9][P], rule 1 mats and G [E][9][q1^3]
 template <typename T>
-hipError_t launch_advect(const sem_mesh* m, int rule, const T* mats, const T* D, const T* G,
-                         const T* u, const T* f, T* out, hipStream_t s);
+hipError_t launch_advect(const sem_mesh* m, int rule, int nf, const T* mats, const T* D,
+                         const T* G, const T* u, const T* f, T* out, hipStream_t s);
 
 }  // namespace sem

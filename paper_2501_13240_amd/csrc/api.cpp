@@ -825,29 +825,37 @@ static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-sem_status sem_advect(const sem_mesh* m, int32_t rule, const void* u, const void* f, void* out,
-                      sem_prec prec, void* stream) {
+sem_status sem_advect_fields(const sem_mesh* m, int32_t rule, const void* u, int32_t nf,
+                             const void* f, void* out, sem_prec prec, void* stream) {
   if (sem_status st = check_mesh(m)) return st;
   if (rule != SEM_ADV_COLLOCATION && rule != SEM_ADV_DEALIAS)
     return fail(SEM_EINVAL, "unknown quadrature rule");
   const AdvRule* R = m->adv[rule];
   if (!R) return fail(SEM_EINVAL, "rule not set up: call sem_setup_advection first");
+  if (nf < 0) return fail(SEM_EINVAL, "nf must be >= 0");
+  if (nf == 0) return SEM_OK;
   if (!u || !f || !out) return fail(SEM_EINVAL, "u, f and out must not be NULL");
   if (prec != SEM_FP64 && prec != SEM_FP32) return fail(SEM_EINVAL, "prec must be FP64 or FP32");
   const size_t sz = prec == SEM_FP64 ? sizeof(double) : sizeof(float), nb = (size_t)m->nL * sz;
-  if (overlaps(out, nb, u, 3 * nb) || overlaps(out, nb, f, nb))
+  if (overlaps(out, nf * nb, u, 3 * nb) || overlaps(out, nf * nb, f, nf * nb))
     return fail(SEM_EINVAL, "out must not overlap u or f");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if (prec == SEM_FP64)
-    e = launch_advect<double>(m, rule, R->mats64.as<double>(), m->D64.as<double>(),
+    e = launch_advect<double>(m, rule, nf, R->mats64.as<double>(), m->D64.as<double>(),
                               R->G64.as<double>(), (const double*)u, (const double*)f,
                               (double*)out, s);
   else
-    e = launch_advect<float>(m, rule, R->mats32.as<float>(), m->D32.as<float>(),
-                             R->G32.as<float>(), (const float*)u, (const float*)f, (float*)out, s);
+    e = launch_advect<float>(m, rule, nf, R->mats32.as<float>(), m->D32.as<float>(),
+                             R->G32.as<float>(), (const float*)u, (const float*)f, (float*)out,
+                             s);
   if (e != hipSuccess) return hip_fail(e, "advect");
   return SEM_OK;
+}
+
+sem_status sem_advect(const sem_mesh* m, int32_t rule, const void* u, const void* f, void* out,
+                      sem_prec prec, void* stream) {
+  return sem_advect_fields(m, rule, u, 1, f, out, prec, stream);
 }
 
 sem_status sem_lmax_estimate(const sem_mesh* m, const double* k, double h2, int32_t steps,

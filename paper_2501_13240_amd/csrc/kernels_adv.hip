@@ -112,13 +112,14 @@ struct Stages {
 
 // Persistent: workgroup b processes elements b, b + grid, ...  The factors a
 // pass consumes are requested one pass ahead (the first pass's during the
-// previous element's f pass and projection), into the registers the
+// previous element's field passes and projections), into the registers the
 // previous pass has just consumed, so the factor stream stays in flight
-// while the matrix cores interpolate.
+// while the matrix cores interpolate.  V is formed once per element and
+// applied to each of the nf fields f[k] (stride E P, like u).
 template <int N, typename T>
 __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
-    int64_t E, const T* __restrict__ mats, const T* __restrict__ G, const T* __restrict__ u,
-    int64_t ustride, const T* __restrict__ f, T* __restrict__ out) {
+    int64_t E, int nf, const T* __restrict__ mats, const T* __restrict__ G,
+    const T* __restrict__ u, int64_t ustride, const T* __restrict__ f, T* __restrict__ out) {
   constexpr int M = (3 * (N + 1)) / 2;
   typedef Stages<N, M, T> S;
   typedef typename S::I0 I0;
@@ -203,77 +204,101 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
       else if (en < E) fetch(en, 0);
     }
 
-    // 2. c = sum_a V_a df/dr_a: r (J x J x JD), s (J x JD x J), t (JD x J x J)
-    FOR_TILES(I0, I0::store(sX0, I0::tile(sIn + 3 * P, aJ, t, lane), t, lane);
-              I0::store(sX1, I0::tile(sIn + 3 * P, aJD, t, lane), t, lane));
-    __syncthreads();
-    V c[TPW];
-#pragma unroll
-    for (int ti = 0; ti < TPW; ++ti) c[ti] = V{T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T* src = a == 0 ? sX1 : sX0;
-      const T* a1 = a == 1 ? aJD : aJ;
-      const T* a2 = a == 2 ? aJD : aJ;
-      FOR_TILES(I1, I1::store(sY, I1::tile(src, a1, t, lane), t, lane));
+    // every field k advected by the same V
+    for (int k = 0; k < nf; ++k) {
+      if (k > 0) {
+        for (int q = threadIdx.x; q < P; q += kAdvThreads)
+          sIn[3 * P + q] = f[k * ustride + e * P + q];
+        __syncthreads();
+      }
+      // 2. c = sum_a V_a df/dr_a: r (J x J x JD), s (J x JD x J), t (JD x J x J)
+      FOR_TILES(I0, I0::store(sX0, I0::tile(sIn + 3 * P, aJ, t, lane), t, lane);
+                I0::store(sX1, I0::tile(sIn + 3 * P, aJD, t, lane), t, lane));
       __syncthreads();
+      V c[TPW];
+#pragma unroll
+      for (int ti = 0; ti < TPW; ++ti) c[ti] = V{T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T* src = a == 0 ? sX1 : sX0;
+        const T* a1 = a == 1 ? aJD : aJ;
+        const T* a2 = a == 2 ? aJD : aJ;
+        FOR_TILES(I1, I1::store(sY, I1::tile(src, a1, t, lane), t, lane));
+        __syncthreads();
+#pragma unroll
+        for (int ti = 0; ti < TPW; ++ti) {
+          const int t = wv + ti * kAdvWaves;
+          if (t < I2::NT) {
+            const V fa = I2::tile(sY, a2, t, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c[ti][r] += Va[ti][a][r] * fa[r];
+          }
+        }
+        __syncthreads();
+      }
+      // c into the first region (its inputs and first-stage arrays are dead)
+      T* sC = sR;
 #pragma unroll
       for (int ti = 0; ti < TPW; ++ti) {
         const int t = wv + ti * kAdvWaves;
-        if (t < I2::NT) {
-          const V fa = I2::tile(sY, a2, t, lane);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) c[ti][r] += Va[ti][a][r] * fa[r];
-        }
+        if (t < I2::NT) I2::store(sC, c[ti], t, lane);
       }
       __syncthreads();
-    }
-    // c into the first region (its inputs and first-stage arrays are dead)
-    T* sC = sR;
-#pragma unroll
-    for (int ti = 0; ti < TPW; ++ti) {
-      const int t = wv + ti * kAdvWaves;
-      if (t < I2::NT) I2::store(sC, c[ti], t, lane);
-    }
-    __syncthreads();
 
-    // 3. out = (J^T x J^T x J^T) c
-    FOR_TILES(B2, B2::store(sY, B2::tile(sC, aJT, t, lane), t, lane));
-    __syncthreads();
-    FOR_TILES(B1, B1::store(sR, B1::tile(sY, aJT, t, lane), t, lane));
-    __syncthreads();
-    FOR_TILES(B0, B0::store(out + e * P, B0::tile(sR, aJT, t, lane), t, lane));
-    __syncthreads();  // the next element restages sR
+      // 3. out = (J^T x J^T x J^T) c
+      FOR_TILES(B2, B2::store(sY, B2::tile(sC, aJT, t, lane), t, lane));
+      __syncthreads();
+      FOR_TILES(B1, B1::store(sR, B1::tile(sY, aJT, t, lane), t, lane));
+      __syncthreads();
+      FOR_TILES(B0, B0::store(out + k * ustride + e * P, B0::tile(sR, aJT, t, lane), t, lane));
+      __syncthreads();  // sR is restaged next
+    }
   }
 }
 
 template <int N, typename T>
 __global__ __launch_bounds__(kAdvThreads) void adv_colloc_kernel(
-    const T* __restrict__ D, const T* __restrict__ G, const T* __restrict__ u, int64_t ustride,
-    const T* __restrict__ f, T* __restrict__ out) {
-  constexpr int n = N + 1, P = n * n * n;
+    int nf, const T* __restrict__ D, const T* __restrict__ G, const T* __restrict__ u,
+    int64_t ustride, const T* __restrict__ f, T* __restrict__ out) {
+  constexpr int n = N + 1, P = n * n * n, PT = (P + kAdvThreads - 1) / kAdvThreads;
   __shared__ T sF[P];
   __shared__ T sD[n * n];
   const int64_t e = blockIdx.x;
-  for (int q = threadIdx.x; q < P; q += kAdvThreads) sF[q] = f[e * P + q];
   for (int q = threadIdx.x; q < n * n; q += kAdvThreads) sD[q] = D[q];
-  __syncthreads();
+  // V_a = sum_d G_ad u_d at this thread's nodes
   const T* Ge = G + e * 9 * P;
-  for (int q = threadIdx.x; q < P; q += kAdvThreads) {
-    const int i = q % n, j = (q / n) % n, k = q / (n * n);
-    T fr = T(0), fs = T(0), ft = T(0);
+  T V[PT][3];
 #pragma unroll
-    for (int l = 0; l < n; ++l) {
-      fr += sD[i * n + l] * sF[(k * n + j) * n + l];
-      fs += sD[j * n + l] * sF[(k * n + l) * n + i];
-      ft += sD[k * n + l] * sF[(l * n + j) * n + i];
+  for (int j = 0; j < PT; ++j) {
+    const int q = threadIdx.x + j * kAdvThreads;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) V[j][a] = T(0);
+    if (q < P)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const T ud = u[d * ustride + e * P + q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) V[j][a] += Ge[(3 * a + d) * P + q] * ud;
+      }
+  }
+  for (int k = 0; k < nf; ++k) {
+    if (k > 0) __syncthreads();  // the previous field's sums are done with sF
+    for (int q = threadIdx.x; q < P; q += kAdvThreads) sF[q] = f[k * ustride + e * P + q];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int q = threadIdx.x + j * kAdvThreads;
+      if (q >= P) continue;
+      const int i = q % n, jj = (q / n) % n, kk = q / (n * n);
+      T fr = T(0), fs = T(0), ft = T(0);
+#pragma unroll
+      for (int l = 0; l < n; ++l) {
+        fr += sD[i * n + l] * sF[(kk * n + jj) * n + l];
+        fs += sD[jj * n + l] * sF[(kk * n + l) * n + i];
+        ft += sD[kk * n + l] * sF[(l * n + jj) * n + i];
+      }
+      out[k * ustride + e * P + q] = V[j][0] * fr + V[j][1] * fs + V[j][2] * ft;
     }
-    T c = T(0);
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      c += u[d * ustride + e * P + q] *
-           (Ge[d * P + q] * fr + Ge[(3 + d) * P + q] * fs + Ge[(6 + d) * P + q] * ft);
-    out[e * P + q] = c;
   }
 }
 
@@ -358,12 +383,12 @@ __global__ void adv_metric_finish(int64_t E, int q1, const double* __restrict__ 
 }
 
 template <int N, typename T>
-hipError_t run_advect(const sem_mesh* m, int rule, const T* mats, const T* D, const T* G,
+hipError_t run_advect(const sem_mesh* m, int rule, int nf, const T* mats, const T* D, const T* G,
                       const T* u, const T* f, T* out, hipStream_t s) {
   const int64_t ustride = m->E * (int64_t)m->P;
   if (rule == 0) {
     hipLaunchKernelGGL((adv_colloc_kernel<N, T>), dim3((unsigned)m->E), dim3(kAdvThreads), 0, s,
-                       D, G, u, ustride, f, out);
+                       nf, D, G, u, ustride, f, out);
     return hipGetLastError();
   }
   // persistent grid: twice the resident workgroups (measured best of 1x, 2x)
@@ -381,7 +406,7 @@ hipError_t run_advect(const sem_mesh* m, int rule, const T* mats, const T* D, co
   int64_t grid = 2 * (int64_t)cus * per_cu;
   if (grid > m->E) grid = m->E;
   hipLaunchKernelGGL((adv_dealias_kernel<N, T>), dim3((unsigned)grid), dim3(kAdvThreads), 0, s,
-                     m->E, mats, G, u, ustride, f, out);
+                     m->E, nf, mats, G, u, ustride, f, out);
   return hipGetLastError();
 }
 
@@ -428,26 +453,27 @@ hipError_t launch_adv_geometry(const sem_mesh* m, int q1, const double* mats, co
 }
 
 template <typename T>
-hipError_t launch_advect(const sem_mesh* m, int rule, const T* mats, const T* D, const T* G,
-                         const T* u, const T* f, T* out, hipStream_t s) {
+hipError_t launch_advect(const sem_mesh* m, int rule, int nf, const T* mats, const T* D,
+                         const T* G, const T* u, const T* f, T* out, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
   switch (m->N) {
-    case 1: return run_advect<1, T>(m, rule, mats, D, G, u, f, out, s);
-    case 2: return run_advect<2, T>(m, rule, mats, D, G, u, f, out, s);
-    case 3: return run_advect<3, T>(m, rule, mats, D, G, u, f, out, s);
-    case 4: return run_advect<4, T>(m, rule, mats, D, G, u, f, out, s);
-    case 5: return run_advect<5, T>(m, rule, mats, D, G, u, f, out, s);
-    case 6: return run_advect<6, T>(m, rule, mats, D, G, u, f, out, s);
-    case 7: return run_advect<7, T>(m, rule, mats, D, G, u, f, out, s);
-    case 8: return run_advect<8, T>(m, rule, mats, D, G, u, f, out, s);
-    case 9: return run_advect<9, T>(m, rule, mats, D, G, u, f, out, s);
-    case 10: return run_advect<10, T>(m, rule, mats, D, G, u, f, out, s);
+    case 1: return run_advect<1, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 2: return run_advect<2, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 3: return run_advect<3, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 4: return run_advect<4, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 5: return run_advect<5, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 6: return run_advect<6, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 7: return run_advect<7, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 8: return run_advect<8, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 9: return run_advect<9, T>(m, rule, nf, mats, D, G, u, f, out, s);
+    case 10: return run_advect<10, T>(m, rule, nf, mats, D, G, u, f, out, s);
     default: return hipErrorInvalidValue;
   }
 }
-template hipError_t launch_advect<double>(const sem_mesh*, int, const double*, const double*,
-                                          const double*, const double*, const double*, double*,
-                                          hipStream_t);
-template hipError_t launch_advect<float>(const sem_mesh*, int, const float*, const float*,
+template hipError_t launch_advect<double>(const sem_mesh*, int, int, const double*,
+                                          const double*, const double*, const double*,
+                                          const double*, double*, hipStream_t);
+template hipError_t launch_advect<float>(const sem_mesh*, int, int, const float*, const float*,
                                          const float*, const float*, const float*, float*,
                                          hipStream_t);
 

@@ -1,5 +1,5 @@
-"""GPU parity of the convective term (sem_setup_advection, sem_advect) with
-the oracle's convect().
+"""GPU parity of the convective term (sem_setup_advection, sem_advect,
+sem_advect_fields) with the oracle's convect().
 
 Tolerances (max-norm error relative to the largest reference value):
   factors w detJ dr_a/dx_d, FP64      <= 1e-12
@@ -112,10 +112,16 @@ def test_full_size_convection_box_sampled():
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
     idx = np.sort(np.random.default_rng(4).choice(m.E, 48, replace=False))
     idx[-1] = m.E - 1
+    sel = torch.as_tensor(idx, device="cuda")
     for rule, de in RULES.items():
-        out = sem.advect(M, dev(u), dev(f), rule=rule)[torch.as_tensor(idx, device="cuda")]
+        out = sem.advect(M, dev(u), dev(f), rule=rule)[sel]
         ref = convect(np.moveaxis(u[:, idx], 0, 2), f[idx], m.xyz[idx], N, dealias=de)
         assert relmax(out.cpu().numpy(), ref) <= 1e-12
+        # the four fields of a Boussinesq step in one call
+        many = sem.advect(M, dev(u), dev(np.concatenate([f[None], u])), rule=rule)[:, sel]
+        for k in range(1, 4):
+            ref = convect(np.moveaxis(u[:, idx], 0, 2), u[k - 1, idx], m.xyz[idx], N, dealias=de)
+            assert relmax(many[k].cpu().numpy(), ref) <= 1e-12
 
 
 def test_errors():
@@ -153,3 +159,46 @@ def test_errors():
         sem.advect(M, ud[:2], fd)
     with pytest.raises(sem.SemError):
         sem.advect(M, ud, fd, out=fd)
+
+
+@pytest.mark.parametrize("rule", list(RULES))
+@pytest.mark.parametrize("N", [2, 7, 9])
+def test_advect_fields_equals_one_field_calls_and_oracle(N, rule):
+    # a Boussinesq step's four advected fields: T and the velocity components
+    m, u, T = _case(N, shape=(3, 2, 4))
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    fields = np.concatenate([T[None], u])
+    for dt in (torch.float64, torch.float32):
+        ud, fd = dev(u, dt), dev(fields, dt)
+        many = sem.advect(M, ud, fd, rule=rule)
+        for k in range(4):
+            one = sem.advect(M, ud, fd[k].contiguous(), rule=rule)
+            assert torch.equal(many[k], one)
+    ref = np.stack([convect(np.moveaxis(u, 0, 2), fk, m.xyz, N, dealias=RULES[rule])
+                    for fk in fields])
+    got = sem.advect(M, dev(u), dev(fields), rule=rule).cpu().numpy()
+    for k in range(4):
+        assert relmax(got[k], ref[k]) <= 1e-12
+
+
+def test_advect_fields_arguments():
+    N = 3
+    m, u, f = _case(N)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    M.setup_advection("dealias")
+    lib = L.load()
+    ud, fd = dev(u), dev(np.stack([f, 2 * f]))
+    out = torch.full_like(fd, 7.0)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.sem_advect_fields(M.handle, 1, ptr(ud), 0, ptr(fd), ptr(out), 0, s) == L.SEM_OK
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())  # nf = 0 writes nothing
+    assert lib.sem_advect_fields(M.handle, 1, ptr(ud), -1, ptr(fd), ptr(out), 0, s) == \
+        L.SEM_EINVAL
+    # out[0] overlapping f[1]
+    assert lib.sem_advect_fields(M.handle, 1, ptr(ud), 2, ptr(fd), ptr(fd[1]), 0, s) == \
+        L.SEM_EINVAL
+    assert lib.sem_advect_fields(M.handle, 1, ptr(ud), 2, ptr(fd), ptr(out), 0, s) == L.SEM_OK
+    torch.cuda.synchronize()
+    assert torch.allclose(out[1], 2 * out[0], rtol=1e-14, atol=0)
