@@ -134,8 +134,14 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
   // (n,n,M) projection stage
   constexpr int R0 = 4 * P + 2 * n * n * M;
   static_assert(Q <= R0, "c fits the first region");
+  // FP64: the f pass forms its three (n,M,M) arrays in one phase when they
+  // fit beside the rest with two workgroups per CU (two barriers per field
+  // instead of six; measured 3.5 % faster with four fields at N = 7).  FP32
+  // keeps one array: the larger LDS and register footprint cost it a wave
+  // per SIMD (27 % slower)
+  constexpr bool kMerge = sizeof(T) == 8 && (R0 + 3 * S::YS) * sizeof(T) <= 80 * 1024;
   __shared__ T sR[R0];
-  __shared__ T sY[S::YS];
+  __shared__ T sY[kMerge ? 3 * S::YS : S::YS];
   T* sIn = sR;  // u_x, u_y, u_z, f
   T* sX0 = sR + 4 * P;
   T* sX1 = sX0 + n * n * M;
@@ -218,23 +224,47 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
       V c[TPW];
 #pragma unroll
       for (int ti = 0; ti < TPW; ++ti) c[ti] = V{T(0), T(0), T(0), T(0)};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const T* src = a == 0 ? sX1 : sX0;
-        const T* a1 = a == 1 ? aJD : aJ;
-        const T* a2 = a == 2 ? aJD : aJ;
-        FOR_TILES(I1, I1::store(sY, I1::tile(src, a1, t, lane), t, lane));
+      if constexpr (kMerge) {
+        FOR_TILES(I1, I1::store(sY, I1::tile(sX1, aJ, t, lane), t, lane);
+                  I1::store(sY + S::YS, I1::tile(sX0, aJD, t, lane), t, lane);
+                  I1::store(sY + 2 * S::YS, I1::tile(sX0, aJ, t, lane), t, lane));
         __syncthreads();
 #pragma unroll
         for (int ti = 0; ti < TPW; ++ti) {
           const int t = wv + ti * kAdvWaves;
           if (t < I2::NT) {
-            const V fa = I2::tile(sY, a2, t, lane);
+            // one derivative tile live at a time (the scheduler would
+            // otherwise hoist all of them and halve the occupancy)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) c[ti][r] += Va[ti][a][r] * fa[r];
+            for (int a = 0; a < 3; ++a) {
+              const V fa = I2::tile(sY + a * S::YS, a == 2 ? aJD : aJ, t, lane);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) c[ti][r] += Va[ti][a][r] * fa[r];
+              __builtin_amdgcn_sched_barrier(0);
+            }
           }
         }
-        __syncthreads();
+        // (the c stores below touch sR only, whose arrays the phase above read
+        // before the barrier)
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const T* src = a == 0 ? sX1 : sX0;
+          const T* a1 = a == 1 ? aJD : aJ;
+          const T* a2 = a == 2 ? aJD : aJ;
+          FOR_TILES(I1, I1::store(sY, I1::tile(src, a1, t, lane), t, lane));
+          __syncthreads();
+#pragma unroll
+          for (int ti = 0; ti < TPW; ++ti) {
+            const int t = wv + ti * kAdvWaves;
+            if (t < I2::NT) {
+              const V fa = I2::tile(sY, a2, t, lane);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) c[ti][r] += Va[ti][a][r] * fa[r];
+            }
+          }
+          __syncthreads();
+        }
       }
       // c into the first region (its inputs and first-stage arrays are dead)
       T* sC = sR;
