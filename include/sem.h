@@ -158,8 +158,10 @@ sem_status sem_gll(int32_t N, double* xi, double* rho, double* D);
 
 /* HOST-only.  The numbering sem_setup_mesh builds from gid/dirichlet:
  * free_index[E*P] (HOST, caller-allocated) receives for each local point the
- * index of its free unique node in first-touch order, or -1 for Dirichlet
- * nodes; n_unique / n_free / n_shared receive the counts.  Validates as
+ * index of its free unique node, or -1 for Dirichlet nodes: the free nodes
+ * with a single local copy come first, then those with several, each class
+ * in first-touch order (the order of first appearance in the local points);
+ * n_unique / n_free / n_shared receive the counts.  Validates as
  * sem_setup_mesh does (gid >= 0, consistent Dirichlet flags). */
 sem_status sem_host_numbering(int32_t N, int64_t E, const int64_t* gid, const uint8_t* dirichlet,
                               int32_t* free_index, int64_t* n_unique, int64_t* n_free,

@@ -448,6 +448,16 @@ sem_status sem_setup_mesh(const sem_mesh_desc* desc, void* stream, sem_mesh** ou
       return fail(SEM_EINVAL, "element map is not orientation-preserving (detJ <= 0) at " +
                                   std::to_string(bad) + " points");
   }
+  // routing of the in-solve operator: single-copy free nodes are written
+  // straight to the free vector, shared ones through the segmented sum (the
+  // host array lives until the stream is synchronised below)
+  std::vector<int32_t> lmap2(hn.lmap.size());
+  for (size_t q = 0; q < hn.lmap.size(); ++q) {
+    const int32_t v = hn.lmap[q];
+    lmap2[q] = v < 0 ? -1 : v < hn.n_single ? v : -(v + 2);
+  }
+  m->n_single = hn.n_single;
+  if ((st = upload(m->lmap2, lmap2, s))) return st;
   if ((st = upload(m->lmap, hn.lmap, s)) || (st = upload(m->fseg, hn.fseg, s)) ||
       (st = upload(m->fperm, hn.fperm, s)) || (st = upload(m->gseg, hn.gseg, s)) ||
       (st = upload(m->gperm, hn.gperm, s)) || (st = upload(m->dlist, hn.dlist, s)))

@@ -68,7 +68,9 @@ struct DevBuf {
 // ----------------------------------------------------------- host numbering
 struct HostNumbering {
   int64_t n_unique = 0, n_free = 0, n_shared = 0;
-  std::vector<int32_t> lmap;          // [nL] free index (first-touch order) or -1
+  int64_t n_single = 0;               // free nodes with one local copy: indices [0, n_single)
+  std::vector<int32_t> lmap;          // [nL] free index or -1: single-copy nodes first, then
+                                      // shared ones, each class in first-touch order
   std::vector<int32_t> fseg, fperm;   // CSR over free unique nodes -> local copies (ascending)
   std::vector<int32_t> gseg, gperm;   // CSR over shared unique nodes (all, incl. Dirichlet)
   std::vector<int32_t> dlist;         // local indices of Dirichlet copies
@@ -169,6 +171,8 @@ struct sem_mesh {
   sem::DevBuf D64, D32;                 // derivative matrix
   sem::DevBuf G64, B64, G32, B32;       // geometry [E][6][P], [E][P]
   sem::DevBuf lmap, fseg, fperm;        // solver numbering (free unique nodes)
+  sem::DevBuf lmap2;                    // in-solve operator routing (see launch_ax_split)
+  int64_t n_single = 0;                 // free nodes [0, n_single) have one local copy
   sem::DevBuf gseg, gperm, dlist;       // local gather-scatter tables, Dirichlet copies
   sem::DevBuf fcount;                   // copies per free node as double (for averaging)
   // cached Jacobi inverse and Chebyshev bound for k == NULL
@@ -196,6 +200,18 @@ template <typename T>
 hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
                      const T* G, const T* B, const T* D, hipStream_t s,
                      const int32_t* skip = nullptr, int lp = 0);
+// In-solve operator with split output (matrix-core kernel, N >= 5, FP64 or
+// FP32 contractions): u gathered from the free vector through m->lmap2;
+// results at free nodes with one local copy go straight to wf (free
+// vector), at shared free nodes to wL (local, for the segmented sum over
+// [n_single, n_free)); epart[3 e + {0, 1, 2}] = the element's sums of u w, w and u
+// over its single-copy nodes.  hipErrorNotSupported when unavailable (see
+// ax_split_available).
+template <typename T>
+hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart,
+                           const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
+                           const int32_t* skip);
+bool ax_split_available(const sem_mesh* m);
 hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
                           hipStream_t s);
 template <typename T>

@@ -8,9 +8,12 @@
 // -N(N+1)/4 and +N(N+1)/4 in the corners and 0 elsewhere on the diagonal.
 //
 // Numbering: local points are visited in ascending local index; each global
-// id gets a dense index at its first visit ("first-touch" order), so the
-// unique vectors of the solver follow the element order of the mesh and the
-// gathers of the operator stay local in memory.  Segments list the local
+// id gets a dense index at its first visit ("first-touch" order).  Free
+// indices put the nodes with a single local copy (element interiors) first
+// and the shared ones after them, each class in first-touch order, so the
+// unique vectors of the solver follow the element order of the mesh, the
+// operator's gathers and direct stores run over contiguous stretches, and
+// the segmented sum covers one contiguous range.  Segments list the local
 // copies of each node in ascending order (counting sort, O(n_L)).
 #include <algorithm>
 #include <cmath>
@@ -144,18 +147,29 @@ sem_status build_numbering(int N, int64_t E, const int64_t* gid, const uint8_t* 
     mult[uidx[q]]++;
     if (dirichlet && dirichlet[q]) dcount[uidx[q]]++;
   }
-  int64_t nfree = 0, nshared = 0;
-  std::vector<int32_t> fidx(nu, -1), sidx(nu, -1);
+  // free indices: nodes with one local copy first, then the shared ones,
+  // each class in first-touch order (an element's own nodes are then one
+  // contiguous run, and the shared ones a contiguous range)
+  int64_t nfree = 0, nshared = 0, nsingle = 0;
   for (int64_t u = 0; u < nu; ++u) {
     if (dcount[u] != 0 && dcount[u] != mult[u])
       return fail(SEM_EINVAL, "Dirichlet flag differs between copies of global node " +
                                   std::to_string(u));
-    if (dcount[u] == 0) fidx[u] = (int32_t)nfree++;
+    if (dcount[u] == 0 && mult[u] == 1) ++nsingle;
+  }
+  std::vector<int32_t> fidx(nu, -1), sidx(nu, -1);
+  int64_t next_single = 0, next_shared = nsingle;
+  for (int64_t u = 0; u < nu; ++u) {
+    if (dcount[u] == 0) {
+      fidx[u] = (int32_t)(mult[u] == 1 ? next_single++ : next_shared++);
+      ++nfree;
+    }
     if (mult[u] > 1) sidx[u] = (int32_t)nshared++;
   }
 
   out.n_unique = nu;
   out.n_free = nfree;
+  out.n_single = nsingle;
   out.n_shared = nshared;
   out.lmap.assign(nL, -1);
   out.fseg.assign(nfree + 1, 0);

@@ -312,6 +312,12 @@ __device__ __forceinline__ float half_block_scale(float m) {
   return ldexpf(1.0f, k);
 }
 
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
@@ -339,11 +345,19 @@ struct MShape {
 // bfloat16 / half operands for D, the u block and each v_a block, FP32
 // accumulation; for half each block is scaled by its power-of-two block
 // scale, whose maxima are reduced before the barriers the phases already have.
-template <int N, typename T, bool GATHER, int LP>
+// MODE 0: u and w local [E][P].  MODE 1: u gathered from a free vector
+// through lmap.  MODE 2 (in-solve split): lmap holds v >= 0 for a free node v
+// with one local copy, -(v + 2) for a shared free node v, -1 for a Dirichlet
+// copy; single-copy results go straight to the free vector wf[v], shared
+// copies' results to w (local, for the segmented sum), and epart[3 e + a]
+// receives the element's sums of p w, w and p over its single-copy nodes
+// (p = the gathered input), reduced in a fixed order.
+template <int N, typename T, int MODE, int LP>
 __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
     const T* __restrict__ u, const int32_t* __restrict__ lmap, T* __restrict__ w,
     const T* __restrict__ kf, const T h2, const T* __restrict__ G, const T* __restrict__ B,
-    const T* __restrict__ D, const int64_t E, const int32_t* __restrict__ skip) {
+    const T* __restrict__ D, const int64_t E, const int32_t* __restrict__ skip,
+    T* __restrict__ wf, double* __restrict__ epart) {
   using S = MShape<N>;
   constexpr int n1 = S::n1, P = S::P, TPB = S::TPB, PPT = S::PPT, NT = S::NT, KS = S::KS,
                 NW = S::NW;
@@ -361,13 +375,17 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
   (void)E;
 
   T uq[PPT], gq[PPT][6], kq[PPT];
+  int32_t code[PPT];
+  (void)code;
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
     const int qr = t + s * TPB;
     const int q = qr < P ? qr : P - 1;
     const int64_t idx = e * P + q;
-    if constexpr (GATHER) {
-      const int32_t lm = ld_stream(lmap + idx);
+    if constexpr (MODE >= 1) {
+      const int32_t lv = ld_stream(lmap + idx);
+      const int32_t lm = MODE == 2 ? (lv >= 0 ? lv : lv <= -2 ? -(lv + 2) : -1) : lv;
+      if constexpr (MODE == 2) code[s] = qr < P ? lv : -1;
       const T v = u[lm >= 0 ? lm : 0];
       uq[s] = lm >= 0 ? v : T(0);
     } else {
@@ -502,6 +520,8 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
       contract_tile16<n1, LP, 2, true>(sa[2], so, at16, tile, lane, sc[2], 1.0f / sc[2]);
   }
   __syncthreads();
+  double ps[3] = {0.0, 0.0, 0.0};
+  (void)ps;
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
     const int q = t + s * TPB;
@@ -509,7 +529,34 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
       const int64_t idx = e * P + q;
       T acc = so[q];
       if (use_h2) acc += h2 * ld_stream(B + idx) * uq[s];
-      st_stream(acc, w + idx);
+      if constexpr (MODE == 2) {
+        const int32_t c = code[s];
+        if (c >= 0) {
+          st_stream(acc, wf + c);
+          ps[0] += (double)uq[s] * (double)acc;
+          ps[1] += (double)acc;
+          ps[2] += (double)uq[s];
+        } else if (c <= -2) {
+          st_stream(acc, w + idx);
+        }
+      } else {
+        st_stream(acc, w + idx);
+      }
+    }
+  }
+  if constexpr (MODE == 2) {
+    __shared__ double sred[3][NW];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double x = wave_sum_d(ps[a]);
+      if (lane == 0) sred[a][wv] = x;
+    }
+    __syncthreads();
+    if (t < 3) {
+      double x = 0.0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) x += sred[t][v];
+      epart[3 * e + t] = x;
     }
   }
 }
@@ -608,11 +655,11 @@ hipError_t run_ax_mfma(const sem_mesh* m, const T* u, const int32_t* lmap, T* w,
                        const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip) {
   using M = MShape<N>;
   if (lmap)
-    hipLaunchKernelGGL((ax_mfma_kernel<N, T, true, LP>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                       u, lmap, w, k, h2, G, B, D, m->E, skip);
+    hipLaunchKernelGGL((ax_mfma_kernel<N, T, 1, LP>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                       u, lmap, w, k, h2, G, B, D, m->E, skip, (T*)nullptr, (double*)nullptr);
   else
-    hipLaunchKernelGGL((ax_mfma_kernel<N, T, false, LP>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                       u, lmap, w, k, h2, G, B, D, m->E, skip);
+    hipLaunchKernelGGL((ax_mfma_kernel<N, T, 0, LP>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                       u, lmap, w, k, h2, G, B, D, m->E, skip, (T*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
 
@@ -677,6 +724,51 @@ template hipError_t launch_ax<double>(const sem_mesh*, const double*, const int3
 template hipError_t launch_ax<float>(const sem_mesh*, const float*, const int32_t*, float*,
                                      const float*, float, const float*, const float*,
                                      const float*, hipStream_t, const int32_t*, int);
+
+namespace {
+template <int N, typename T>
+hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart, const T* k,
+                        T h2, const T* G, const T* B, const T* D, hipStream_t s,
+                        const int32_t* skip) {
+  if constexpr (has_mfma(N)) {
+    using M = MShape<N>;
+    hipLaunchKernelGGL((ax_mfma_kernel<N, T, 2, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s, u,
+                       m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+    return hipGetLastError();
+  } else {
+    return hipErrorNotSupported;
+  }
+}
+}  // namespace
+
+bool ax_split_available(const sem_mesh* m) {
+  if (!has_mfma(m->N) || !m->lmap2.p) return false;
+  const AxChoice c = ax_choice();
+  return c == AxChoice::Auto ? prefer_mfma(m->N, true, false) : c == AxChoice::Mfma;
+}
+
+template <typename T>
+hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart,
+                           const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
+                           const int32_t* skip) {
+  if (!ax_split_available(m)) return hipErrorNotSupported;
+  switch (m->N) {
+    case 5: return run_ax_split<5, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
+    case 6: return run_ax_split<6, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
+    case 7: return run_ax_split<7, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
+    case 8: return run_ax_split<8, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
+    case 9: return run_ax_split<9, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
+    case 10: return run_ax_split<10, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
+    default: return hipErrorNotSupported;
+  }
+}
+template hipError_t launch_ax_split<double>(const sem_mesh*, const double*, double*, double*,
+                                            double*, const double*, double, const double*,
+                                            const double*, const double*, hipStream_t,
+                                            const int32_t*);
+template hipError_t launch_ax_split<float>(const sem_mesh*, const float*, float*, float*, double*,
+                                           const float*, float, const float*, const float*,
+                                           const float*, hipStream_t, const int32_t*);
 
 hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
                           hipStream_t s) {

@@ -3,10 +3,11 @@
 // (Sec. 2.2), FP32 preconditioner work (Sec. 2.2), and FP64 iterative
 // refinement around an FP32 inner solve.
 //
-// Vectors of the solve live on the free unique nodes in first-touch order
-// (length n_free).  One iteration is
-//   ax (gathers p through lmap, writes the element-local result w_L)
-//   -> segmented sum w = R Q^T w_L fused with p.w
+// Vectors of the solve live on the free unique nodes (length n_free; the
+// n_single nodes with one local copy first).  One iteration is
+//   ax (gathers p through lmap, writes the element-local result w_L; from
+//   N = 5 on it writes w at the single-copy nodes directly, with their p.w)
+//   -> segmented sum w = R Q^T w_L fused with p.w (over the shared nodes)
 //   -> alpha on the device -> x, r update fused with r.r (and r.S r)
 //   -> beta on the device -> p update.
 // All scalars stay on the device (CgScalars); the host only polls the `done`
@@ -106,6 +107,40 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t
   if (sc->done) return;
   double v[3] = {0.0, 0.0, 0.0};
   BLOCK_CHUNK(g, nf) {
+    const T s = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
+    w[g] = s;
+    const double pg = (double)p[g];
+    v[0] += pg * (double)s;
+    v[1] += (double)s;
+    v[2] += pg;
+  }
+  block_partials<3>(v, part);
+}
+
+// The same for the split operator, which has already written w at the
+// single-copy free nodes [0, n1) and their partials per element: segmented
+// sums over the shared free nodes [n1, nf) only, plus this block's chunk of
+// the element partials (in element order, so the totals stay deterministic).
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
+    int64_t n1, int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
+    const T* __restrict__ wL, const T* __restrict__ p, T* __restrict__ w, int64_t E,
+    const double* __restrict__ epart, double* __restrict__ part,
+    const CgScalars* __restrict__ sc) {
+  if (sc->done) return;
+  double v[3] = {0.0, 0.0, 0.0};
+  {
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t ch = (E + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = lb * ch, hi = lo + ch < E ? lo + ch : E;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+      v[0] += epart[3 * e];
+      v[1] += epart[3 * e + 1];
+      v[2] += epart[3 * e + 2];
+    }
+  }
+  BLOCK_CHUNK(i, nf - n1) {
+    const int64_t g = n1 + i;
     const T s = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
     w[g] = s;
     const double pg = (double)p[g];
@@ -592,7 +627,7 @@ static sem_status remove_mean(const sem_mesh* m, SolveWork& W, T* a, hipStream_t
 
 template <typename T>
 sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* xf, T* wL,
-                    hipStream_t s, bool timed) {
+                    hipStream_t s, bool timed, T* wf, double* epart) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     if (W.ev_used + 2 > (int)W.ev.size()) {
@@ -608,16 +643,17 @@ sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* x
     SEM_HIP(hipEventRecord(e0, s));
   }
   hipError_t e =
-      launch_ax<T>(m, xf, m->lmap.as<int32_t>(), wL, op.k, op.h2, op.G, op.B, op.D, s, op.skip,
-                   op.lp);
+      wf ? launch_ax_split<T>(m, xf, wf, wL, epart, op.k, op.h2, op.G, op.B, op.D, s, op.skip)
+         : launch_ax<T>(m, xf, m->lmap.as<int32_t>(), wL, op.k, op.h2, op.G, op.B, op.D, s,
+                        op.skip, op.lp);
   if (e != hipSuccess) return hip_fail(e, "operator kernel");
   if (timed) SEM_HIP(hipEventRecord(e1, s));
   return SEM_OK;
 }
 template sem_status apply_op<double>(const sem_mesh*, SolveWork&, const Op<double>&, const double*,
-                                     double*, hipStream_t, bool);
+                                     double*, hipStream_t, bool, double*, double*);
 template sem_status apply_op<float>(const sem_mesh*, SolveWork&, const Op<float>&, const float*,
-                                    float*, hipStream_t, bool);
+                                    float*, hipStream_t, bool, float*, double*);
 
 // ------------------------------------------------------ Chebyshev on device
 
@@ -788,11 +824,22 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   double* partA = part;
   double* partB = part + kReduceBlocks * kMaxReduce;
   double* partC = part + 2 * kReduceBlocks * kMaxReduce;
+  // single-copy free nodes leave the operator directly (see launch_ax_split)
+  const bool split = op_it.lp == 0 && ax_split_available(m);
+  double* epart = split ? W.vec<double>(W.epart, 3 * m->E) : nullptr;
+  if (split && !epart) return fail(SEM_ENOMEM, "work space");
   auto iteration = [&](hipStream_t ss) -> sem_status {
     sem_status e;
-    if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile))) return e;
-    hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, m->fseg.as<int32_t>(),
-                       m->fperm.as<int32_t>(), wL, p, w, partA, sc);
+    if (split) {
+      if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile, w, epart))) return e;
+      hipLaunchKernelGGL((k_gsum_split_pw<T>), dim3(nb), dim3(kVecBlock), 0, ss, m->n_single,
+                         nf, m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, p, w, m->E,
+                         epart, partA, sc);
+    } else {
+      if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile))) return e;
+      hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, ss, nf,
+                         m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, p, w, partA, sc);
+    }
     if (jac) {
       hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
                          a.dinv, partA, (int)nb, partB, sc, ahist);

@@ -14,7 +14,7 @@ struct SolveWork {
   DevBuf bf, x, r, p, w, z, wL, dinv, tmpf;          // FP64
   DevBuf x32, r32, ri32, p32, w32, z32, wL32, dinv32, k32; // FP32
   DevBuf cd, crk, cd32, crk32;                       // Chebyshev d and r_k
-  DevBuf part, sc, red, hist, ahist, bhist;
+  DevBuf part, sc, red, hist, ahist, bhist, epart;
   CgScalars* h_sc = nullptr;  // pinned: [0..1] polling slots, [3] upload
   double* h_red = nullptr;    // pinned reduction results
   std::vector<hipEvent_t> ev; // profiling events
@@ -89,7 +89,7 @@ struct CgArgs {
 
 template <typename T>
 sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* xf, T* wL,
-                    hipStream_t s, bool timed);
+                    hipStream_t s, bool timed, T* wf = nullptr, double* epart = nullptr);
 
 template <typename Tr, typename Tp>
 sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,

@@ -118,11 +118,16 @@ def test_numbering_counts_and_first_touch(cfg):
     for g, f in zip(m.gid.ravel(), fi.ravel()):
         if f >= 0:
             assert first.setdefault(g, f) == f
-    # first-touch order: free indices appear in increasing order of first visit
+    # single-copy nodes first, then shared ones, each class in first-touch
+    # order: within a class, free indices increase with the first visit
     seen = fi.ravel()[fi.ravel() >= 0]
-    _, idx = np.unique(seen, return_index=True)
-    assert np.all(np.diff(np.sort(idx)) > 0)
-    assert np.all(seen[np.sort(idx)] == np.arange(nf))
+    _, first_visit = np.unique(seen, return_index=True)  # per free index
+    copies = np.bincount(seen, minlength=nf)
+    n1 = int(np.sum(copies == 1))
+    assert np.all(copies[:n1] == 1) and np.all(copies[n1:] > 1)
+    assert np.all(np.diff(first_visit[:n1]) > 0) and np.all(np.diff(first_visit[n1:]) > 0)
+    # element interiors at N = 7 on a 4^3 mesh: 64 elements x 6^3 nodes
+    assert n1 == 64 * (m.N - 1) ** 3
 
 
 def test_numbering_periodic_and_shared_counts():
