@@ -484,7 +484,9 @@ def main():
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": counter_traffic(),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": f"{ax_kernel_name(M.N)}<{M.N},double,gather> (element operator, 64 B/local point)",
+            "kernel": (f"{ax_kernel_name(M.N)}<{M.N},double,in-solve> (element operator: p gathered, "
+                       "w to the free vector at single-copy nodes and to the local vector at "
+                       "shared ones; 64 B/local point)"),
             "avg_launch_us": ax_avg_ms * 1e3,
             "launches_timed": ax_n,
         },
