@@ -451,13 +451,23 @@ sem_status sem_setup_mesh(const sem_mesh_desc* desc, void* stream, sem_mesh** ou
   // routing of the in-solve operator: single-copy free nodes are written
   // straight to the free vector, shared ones through the segmented sum (the
   // host array lives until the stream is synchronised below)
-  std::vector<int32_t> lmap2(hn.lmap.size());
+  std::vector<int32_t> lmap2(hn.lmap.size()), fperm2(hn.fperm);
   for (size_t q = 0; q < hn.lmap.size(); ++q) {
     const int32_t v = hn.lmap[q];
     lmap2[q] = v < 0 ? -1 : v < hn.n_single ? v : -(v + 2);
   }
+  // shared copies are stored at their element's surface slots
+  bool surf = true;
+  for (int64_t a = hn.fseg[hn.n_single]; a < (int64_t)fperm2.size() && surf; ++a) {
+    const int64_t q = fperm2[a];
+    const int64_t e = q / P, ql = q - e * P;
+    const int r = surface_rank((int)(ql % n1), (int)((ql / n1) % n1), (int)(ql / (n1 * n1)), N);
+    if (r < 0) surf = false;
+    else fperm2[a] = (int32_t)(e * P + r);
+  }
   m->n_single = hn.n_single;
-  if ((st = upload(m->lmap2, lmap2, s))) return st;
+  m->split_ok = surf;
+  if ((st = upload(m->lmap2, lmap2, s)) || (st = upload(m->fperm2, fperm2, s))) return st;
   if ((st = upload(m->lmap, hn.lmap, s)) || (st = upload(m->fseg, hn.fseg, s)) ||
       (st = upload(m->fperm, hn.fperm, s)) || (st = upload(m->gseg, hn.gseg, s)) ||
       (st = upload(m->gperm, hn.gperm, s)) || (st = upload(m->dlist, hn.dlist, s)))

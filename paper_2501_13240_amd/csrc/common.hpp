@@ -155,6 +155,27 @@ __device__ __forceinline__ Tacc segment_sum(const int32_t* __restrict__ perm,
   return s;
 }
 
+// Position of point (i, j, k) of an order-N element among the element's
+// surface points, in a fixed order: the k = 0 layer, then for k = 1..N-1 the
+// ring of the layer (row j = 0, the two end points of rows 1..N-1, row j =
+// N), then the k = N layer; -1 for an interior point.  The surface has
+// 2 (N+1)^2 + 4 N (N-1) points.  The in-solve operator stores shared copies
+// at this position of the element's local block (see launch_ax_split).
+__host__ __device__ inline int surface_rank(int i, int j, int k, int N) {
+  const int n = N + 1;
+  if (k == 0) return j * n + i;
+  if (k == N) return n * n + (N - 1) * 4 * N + j * n + i;
+  const int base = n * n + (k - 1) * 4 * N;
+  if (j == 0) return base + i;
+  if (j == N) return base + n + 2 * (N - 1) + i;
+  if (i == 0) return base + n + 2 * (j - 1);
+  if (i == N) return base + n + 2 * (j - 1) + 1;
+  return -1;
+}
+__host__ __device__ constexpr int surface_points(int N) {
+  return 2 * (N + 1) * (N + 1) + 4 * N * (N - 1);
+}
+
 // ------------------------------------------------------------- the mesh
 struct SolveWork;
 struct Pmg;
@@ -172,7 +193,9 @@ struct sem_mesh {
   sem::DevBuf G64, B64, G32, B32;       // geometry [E][6][P], [E][P]
   sem::DevBuf lmap, fseg, fperm;        // solver numbering (free unique nodes)
   sem::DevBuf lmap2;                    // in-solve operator routing (see launch_ax_split)
+  sem::DevBuf fperm2;                   // fperm with shared copies at their surface slots
   int64_t n_single = 0;                 // free nodes [0, n_single) have one local copy
+  bool split_ok = false;                // every shared copy lies on its element's surface
   sem::DevBuf gseg, gperm, dlist;       // local gather-scatter tables, Dirichlet copies
   sem::DevBuf fcount;                   // copies per free node as double (for averaging)
   // cached Jacobi inverse and Chebyshev bound for k == NULL
@@ -203,8 +226,9 @@ hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, c
 // In-solve operator with split output (matrix-core kernel, N >= 5, FP64 or
 // FP32 contractions): u gathered from the free vector through m->lmap2;
 // results at free nodes with one local copy go straight to wf (free
-// vector), at shared free nodes to wL (local, for the segmented sum over
-// [n_single, n_free)); epart[3 e + {0, 1, 2}] = the element's sums of u w, w and u
+// vector), at shared free nodes to wL at e P + surface_rank (local, for the
+// segmented sum over [n_single, n_free) through fperm2); epart[3 e + {0, 1,
+// 2}] = the element's sums of u w, w and u
 // over its single-copy nodes.  hipErrorNotSupported when unavailable (see
 // ax_split_available).
 template <typename T>

@@ -537,7 +537,8 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
           ps[1] += (double)acc;
           ps[2] += (double)uq[s];
         } else if (c <= -2) {
-          st_stream(acc, w + idx);
+          // shared copy: at its surface slot of the element's block
+          st_stream(acc, w + e * P + surface_rank(q % n1, (q / n1) % n1, q / (n1 * n1), N));
         }
       } else {
         st_stream(acc, w + idx);
@@ -742,7 +743,7 @@ hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epa
 }  // namespace
 
 bool ax_split_available(const sem_mesh* m) {
-  if (!has_mfma(m->N) || !m->lmap2.p) return false;
+  if (!has_mfma(m->N) || !m->lmap2.p || !m->split_ok) return false;
   const AxChoice c = ax_choice();
   return c == AxChoice::Auto ? prefer_mfma(m->N, true, false) : c == AxChoice::Mfma;
 }

@@ -833,7 +833,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
     if (split) {
       if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile, w, epart))) return e;
       hipLaunchKernelGGL((k_gsum_split_pw<T>), dim3(nb), dim3(kVecBlock), 0, ss, m->n_single,
-                         nf, m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, p, w, m->E,
+                         nf, m->fseg.as<int32_t>(), m->fperm2.as<int32_t>(), wL, p, w, m->E,
                          epart, partA, sc);
     } else {
       if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile))) return e;
