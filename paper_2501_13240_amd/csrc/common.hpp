@@ -227,15 +227,16 @@ hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, c
 // FP32 contractions): u gathered from the free vector through m->lmap2;
 // results at free nodes with one local copy go straight to wf (free
 // vector), at shared free nodes to wL at e P + surface_rank (local, for the
-// segmented sum over [n_single, n_free) through fperm2); epart[3 e + {0, 1,
-// 2}] = the element's sums of u w, w and u
-// over its single-copy nodes.  hipErrorNotSupported when unavailable (see
-// ax_split_available).
+// segmented sum over [n_single, n_free) through fperm2); epart[3 (parts e +
+// i) + {0, 1, 2}] (parts = ax_split_parts(N), one per wavefront i) = the
+// sums of u w, w and u over the single-copy nodes.  hipErrorNotSupported
+// when unavailable (see ax_split_available).
 template <typename T>
 hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart,
                            const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
                            const int32_t* skip);
 bool ax_split_available(const sem_mesh* m);
+int ax_split_parts(int N);
 hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
                           hipStream_t s);
 template <typename T>

@@ -312,10 +312,27 @@ __device__ __forceinline__ float half_block_scale(float m) {
   return ldexpf(1.0f, k);
 }
 
+// lane i of each row of 16 receives lane i - SHIFT's value (0 below the row)
+template <int SHIFT>
+__device__ __forceinline__ double dpp_row_shr(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x110 + SHIFT, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x110 + SHIFT, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+// Sum over the wavefront, the same on every lane and in a fixed order: a
+// scan within each row of 16 by DPP row shifts (lane 15 of a row ends with
+// the row's sum), then the four rows in order.  (Six cross-lane shuffles
+// per value made the in-solve operator 6 % slower.)
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
+  v += dpp_row_shr<1>(v);
+  v += dpp_row_shr<2>(v);
+  v += dpp_row_shr<4>(v);
+  v += dpp_row_shr<8>(v);
+  return ((lane_value(v, 15) + lane_value(v, 31)) + lane_value(v, 47)) + lane_value(v, 63);
 }
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -349,9 +366,9 @@ struct MShape {
 // through lmap.  MODE 2 (in-solve split): lmap holds v >= 0 for a free node v
 // with one local copy, -(v + 2) for a shared free node v, -1 for a Dirichlet
 // copy; single-copy results go straight to the free vector wf[v], shared
-// copies' results to w (local, for the segmented sum), and epart[3 e + a]
-// receives the element's sums of p w, w and p over its single-copy nodes
-// (p = the gathered input), reduced in a fixed order.
+// copies' results to w (local, for the segmented sum), and epart[3 (NW e +
+// wave) + a] receives each wavefront's sums of p w, w and p over its
+// single-copy nodes (p = the gathered input), reduced in a fixed order.
 template <int N, typename T, int MODE, int LP>
 __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
     const T* __restrict__ u, const int32_t* __restrict__ lmap, T* __restrict__ w,
@@ -546,18 +563,11 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
     }
   }
   if constexpr (MODE == 2) {
-    __shared__ double sred[3][NW];
+    // one triple of sums per wavefront: no barrier, no LDS
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double x = wave_sum_d(ps[a]);
-      if (lane == 0) sred[a][wv] = x;
-    }
-    __syncthreads();
-    if (t < 3) {
-      double x = 0.0;
-#pragma unroll
-      for (int v = 0; v < NW; ++v) x += sred[t][v];
-      epart[3 * e + t] = x;
+      if (lane == 0) epart[(e * NW + wv) * 3 + a] = x;
     }
   }
 }
@@ -741,6 +751,18 @@ hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epa
   }
 }
 }  // namespace
+
+int ax_split_parts(int N) {
+  switch (N) {
+    case 5: return MShape<5>::NW;
+    case 6: return MShape<6>::NW;
+    case 7: return MShape<7>::NW;
+    case 8: return MShape<8>::NW;
+    case 9: return MShape<9>::NW;
+    case 10: return MShape<10>::NW;
+    default: return 0;
+  }
+}
 
 bool ax_split_available(const sem_mesh* m) {
   if (!has_mfma(m->N) || !m->lmap2.p || !m->split_ok) return false;

@@ -118,21 +118,22 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t
 }
 
 // The same for the split operator, which has already written w at the
-// single-copy free nodes [0, n1) and their partials per element: segmented
-// sums over the shared free nodes [n1, nf) only, plus this block's chunk of
-// the element partials (in element order, so the totals stay deterministic).
+// single-copy free nodes [0, n1) and their partial sums (ne triples, one per
+// wavefront of each element): segmented sums over the shared free nodes
+// [n1, nf) only, plus this block's chunk of the partial triples (in order,
+// so the totals stay deterministic).
 template <typename T>
 __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
     int64_t n1, int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
-    const T* __restrict__ wL, const T* __restrict__ p, T* __restrict__ w, int64_t E,
+    const T* __restrict__ wL, const T* __restrict__ p, T* __restrict__ w, int64_t ne,
     const double* __restrict__ epart, double* __restrict__ part,
     const CgScalars* __restrict__ sc) {
   if (sc->done) return;
   double v[3] = {0.0, 0.0, 0.0};
   {
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t ch = (E + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = lb * ch, hi = lo + ch < E ? lo + ch : E;
+    const int64_t ch = (ne + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = lb * ch, hi = lo + ch < ne ? lo + ch : ne;
     for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
       v[0] += epart[3 * e];
       v[1] += epart[3 * e + 1];
@@ -826,14 +827,15 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   double* partC = part + 2 * kReduceBlocks * kMaxReduce;
   // single-copy free nodes leave the operator directly (see launch_ax_split)
   const bool split = op_it.lp == 0 && ax_split_available(m);
-  double* epart = split ? W.vec<double>(W.epart, 3 * m->E) : nullptr;
+  const int64_t nparts = split ? m->E * ax_split_parts(m->N) : 0;
+  double* epart = split ? W.vec<double>(W.epart, 3 * nparts) : nullptr;
   if (split && !epart) return fail(SEM_ENOMEM, "work space");
   auto iteration = [&](hipStream_t ss) -> sem_status {
     sem_status e;
     if (split) {
       if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile, w, epart))) return e;
       hipLaunchKernelGGL((k_gsum_split_pw<T>), dim3(nb), dim3(kVecBlock), 0, ss, m->n_single,
-                         nf, m->fseg.as<int32_t>(), m->fperm2.as<int32_t>(), wL, p, w, m->E,
+                         nf, m->fseg.as<int32_t>(), m->fperm2.as<int32_t>(), wL, p, w, nparts,
                          epart, partA, sc);
     } else {
       if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile))) return e;
