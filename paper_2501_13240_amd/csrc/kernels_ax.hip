@@ -312,28 +312,6 @@ __device__ __forceinline__ float half_block_scale(float m) {
   return ldexpf(1.0f, k);
 }
 
-// lane i of each row of 16 receives lane i - SHIFT's value (0 below the row)
-template <int SHIFT>
-__device__ __forceinline__ double dpp_row_shr(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x110 + SHIFT, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x110 + SHIFT, 0xf, 0xf, true);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double lane_value(double x, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
-                          __builtin_amdgcn_readlane(__double2loint(x), l));
-}
-// Sum over the wavefront, the same on every lane and in a fixed order: a
-// scan within each row of 16 by DPP row shifts (lane 15 of a row ends with
-// the row's sum), then the four rows in order.  (Six cross-lane shuffles
-// per value made the in-solve operator 6 % slower.)
-__device__ __forceinline__ double wave_sum_d(double v) {
-  v += dpp_row_shr<1>(v);
-  v += dpp_row_shr<2>(v);
-  v += dpp_row_shr<4>(v);
-  v += dpp_row_shr<8>(v);
-  return ((lane_value(v, 15) + lane_value(v, 31)) + lane_value(v, 47)) + lane_value(v, 63);
-}
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll

@@ -31,11 +31,7 @@ namespace {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (n); \
        idx += (int64_t)gridDim.x * blockDim.x)
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-  return x;
-}
+__device__ __forceinline__ double wave_sum(double x) { return wave_sum_d(x); }
 
 // per-block partial sums of NV values -> part[blockIdx.x * NV + a]
 template <int NV>
