@@ -11,7 +11,8 @@ value = unique DOF x iterations / second of the timed steps (GDOF/s).
 roofline: the element-operator kernel (the dominant kernel), 64 algorithmic
 bytes per local point (u, six geometric factors, w in FP64) per launch,
 divided by its average duration measured with HIP events on the solve's
-stream inside the timed region.
+stream inside the timed region (around each operator launch of the last
+timed step; the other steps run without events).
 cpu_baseline: the CPU oracle's PCG iteration on a 32x8x16-element sample of
 the same recipe, timed on this host.
 """
@@ -409,13 +410,15 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
+    # The last timed step records a HIP event pair around each of its operator
+    # launches (the roofline's launch time); the others run without them.
     ax_ms, ax_n = 0.0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = step(True)
-        ax_ms += st["ax_ms"]
-        ax_n += st["ax_launches"]
+    for i in range(args.steps):
+        st = step(i == args.steps - 1)
+        ax_ms += st.get("ax_ms", 0.0)
+        ax_n += st.get("ax_launches", 0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps

@@ -16,6 +16,7 @@
 // fixed grid and a fixed summation order, so solves are bit-reproducible.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -26,6 +27,16 @@ namespace sem {
 
 // ---------------------------------------------------------------- helpers
 namespace {
+
+// Largest solve (free nodes) that replays captured iteration graphs:
+// kGraphMaxFree, or the environment variable SEM_GRAPH_MAX_FREE (read once).
+int64_t graph_max_free() {
+  static const int64_t v = [] {
+    const char* e = std::getenv("SEM_GRAPH_MAX_FREE");
+    return e && *e ? (int64_t)std::strtoll(e, nullptr, 10) : kGraphMaxFree;
+  }();
+  return v;
+}
 
 #define GRID_STRIDE(idx, n)                                                        \
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (n); \
@@ -878,7 +889,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
       if (*g) (void)hipGraphExecDestroy(*g);
     }
   } gguard{&gexec};
-  if (!a.profile && nf <= kGraphMaxFree && a.max_it > 0) {
+  if (!a.profile && nf <= graph_max_free() && a.max_it > 0) {
     hipStream_t cs;
     if ((st = W.capture_stream(&cs))) return st;
     SEM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
