@@ -323,3 +323,28 @@ def test_pcg_first_kind_chebyshev_matches_oracle(precond_prec):
     assert st["converged"] == 1 and res <= 1e-10
     assert abs(st["iters"] - ref["iters"]) <= 2
     assert rel(xf, jac["x"]) <= 1e-8
+
+
+@pytest.mark.parametrize("identify_interior", [False, True])
+def test_pcg_split_and_gather_paths_match_oracle(identify_interior):
+    # From N = 5 the in-solve operator writes single-copy nodes straight to the
+    # free vector and shared copies to their element's surface slots.  A mesh
+    # that identifies two element-interior nodes (valid: equal ids are one
+    # unknown) has a shared copy off the surface, so the solve takes the
+    # gather path instead; both must follow the oracle's CG.
+    N = 5
+    m, fld = config_mesh(2, N=N, shape=(4, 4, 4))
+    gid = m.gid.copy()
+    if identify_interior:
+        q = (2 * (N + 1) + 2) * (N + 1) + 2  # i = j = k = 2
+        gid[5, q] = gid[0, q]
+    M = sem.Mesh(m.xyz, gid, m.dirichlet, N)
+    P = oracle.Problem(m.xyz, gid, m.dirichlet, N)
+    bL = fld["b"].copy()
+    if identify_interior:  # keep the right-hand side copy-consistent
+        bL[5, q] = bL[0, q]
+    b_or = P.num.from_local_consistent(bL)
+    ref = P.solve(b_or, rtol=1e-30, max_iter=60, fixed_iters=True)
+    x, st = sem.solve(M, dev(bL), max_iter=60, fixed_iters=True, history=True)
+    np.testing.assert_allclose(st["history"], ref["res_hist"], rtol=1e-8)
+    assert rel(P.num.from_local_consistent(x.cpu().numpy()), ref["x"]) <= 1e-8
