@@ -836,7 +836,8 @@ sem_status sem_get_advection_factors(const sem_mesh* m, int32_t rule, double* G,
   const AdvRule* R = m->adv[rule];
   if (!R) return fail(SEM_EINVAL, "rule not set up: call sem_setup_advection first");
   if (!G) return fail(SEM_EINVAL, "G must not be NULL");
-  SEM_HIP(hipMemcpyAsync(G, R->G64.p, R->G64.bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  const size_t nb = (size_t)m->E * 9 * R->q1 * R->q1 * R->q1 * sizeof(double);
+  SEM_HIP(hipMemcpyAsync(G, R->G64.p, nb, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return SEM_OK;
 }
 
