@@ -325,6 +325,10 @@ static sem_status estimate_lmax_schwarz(Pmg& P, int l, const double* k, double h
   return SEM_OK;
 }
 
+// iterations per chunk of a multigrid-preconditioned solve (one iteration is
+// a few hundred launches)
+constexpr int kPmgMaxChunk = 2;
+
 static bool prec_ok(sem_prec p) {
   return p == SEM_FP64 || p == SEM_FP32 || p == SEM_BF16_MFMA || p == SEM_FP16_MFMA;
 }
@@ -1024,6 +1028,7 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     a.neumann = neumann;
     a.profile = opts.profile != 0;
     a.check_every = opts.check_every;
+    if (pmg) a.max_chunk = kPmgMaxChunk;
     a.hist = opts.residual_history;
     CgResult res;
     if ((st = cg_solve<double, double>(m, W, a, res, s))) return st;
@@ -1068,6 +1073,7 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
     a.fixed = false;
     a.rtol = opts.inner_rtol;
     a.check_every = opts.check_every;
+    if (pmg) a.max_chunk = kPmgMaxChunk;
     double bd[3];
     if ((st = free_dots_f64(m, W, bf, nullptr, bd, s))) return st;
     const double bnorm = std::sqrt(bd[0]);

@@ -877,7 +877,8 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   // once, so overshooting the last iteration costs only empty launches.
   int chunk = a.check_every;
   if (chunk <= 0)
-    chunk = (int)std::max<int64_t>(1, std::min<int64_t>(16, 2000000 / std::max<int64_t>(nf, 1)));
+    chunk = (int)std::max<int64_t>(
+        1, std::min<int64_t>(a.max_chunk, 2000000 / std::max<int64_t>(nf, 1)));
   chunk = std::max(1, std::min(chunk, std::max(a.max_it, 1)));
   // Small problems are launch-bound: capture one chunk of iterations as a HIP
   // graph (the iteration index lives on the device, so the same graph serves

@@ -82,6 +82,11 @@ struct CgArgs {
   bool neumann = false;
   bool profile = false;
   int check_every = 0;
+  // most iterations per chunk (graph capture and read-back interval); a
+  // preconditioner of many launches (multigrid) asks for short chunks so
+  // that neither the capture nor the overshoot past convergence replays
+  // hundreds of launches
+  int max_chunk = 16;
   double* hist = nullptr;                      // host, max_it + 1
   std::vector<double>* alpha_out = nullptr;    // CG coefficients (Lanczos)
   std::vector<double>* beta_out = nullptr;
