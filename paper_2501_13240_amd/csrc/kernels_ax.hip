@@ -24,6 +24,12 @@
 //
 // Per local point the FP64 apply streams u (8 B), six geometric factors
 // (48 B, planar layout [E][6][P]) and w (8 B): 64 B.
+//
+// Inside the CG (N >= 5) the matrix-core kernel also splits its output: the
+// nodes with a single local copy are finished by the element itself, so it
+// stores w there straight into the free vector (with the p.w, w, p sums of
+// the iteration's dot products), and only the shared copies go through the
+// segmented sum, from the element's surface slots.
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
