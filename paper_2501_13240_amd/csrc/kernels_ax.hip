@@ -353,8 +353,15 @@ struct MShape {
 // copies' results to w (local, for the segmented sum), and epart[3 (NW e +
 // wave) + a] receives each wavefront's sums of p w, w and p over its
 // single-copy nodes (p = the gathered input), reduced in a fixed order.
+// Waves per SIMD the split in-solve form asks for: the gather form's
+// occupancy at N = 6 and N = 9, which a few extra registers would cost it
+// (at N = 9, with 512-thread workgroups, one fewer resident workgroup per CU
+// made the kernel 1.8x slower).
+constexpr int split_min_waves(int N) { return N == 6 ? 7 : N == 9 ? 6 : 1; }
+
 template <int N, typename T, int MODE, int LP>
-__global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
+__global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
+    amdgpu_waves_per_eu(MODE == 2 && sizeof(T) == 8 ? split_min_waves(N) : 1))) void ax_mfma_kernel(
     const T* __restrict__ u, const int32_t* __restrict__ lmap, T* __restrict__ w,
     const T* __restrict__ kf, const T h2, const T* __restrict__ G, const T* __restrict__ B,
     const T* __restrict__ D, const int64_t E, const int32_t* __restrict__ skip,
@@ -376,8 +383,9 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
   (void)E;
 
   T uq[PPT], gq[PPT][6], kq[PPT];
-  int32_t code[PPT];
-  (void)code;
+  // MODE 2: each point's routing code, kept in LDS until the stores (in
+  // registers it cost the N = 9 kernel a wave per SIMD)
+  __shared__ int32_t scode[MODE == 2 ? P : 1];
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
     const int qr = t + s * TPB;
@@ -386,7 +394,8 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
     if constexpr (MODE >= 1) {
       const int32_t lv = ld_stream(lmap + idx);
       const int32_t lm = MODE == 2 ? (lv >= 0 ? lv : lv <= -2 ? -(lv + 2) : -1) : lv;
-      if constexpr (MODE == 2) code[s] = qr < P ? lv : -1;
+      if constexpr (MODE == 2)
+        if (qr < P) scode[qr] = lv;
       const T v = u[lm >= 0 ? lm : 0];
       uq[s] = lm >= 0 ? v : T(0);
     } else {
@@ -531,7 +540,7 @@ __global__ __launch_bounds__(MShape<N>::TPB) void ax_mfma_kernel(
       T acc = so[q];
       if (use_h2) acc += h2 * ld_stream(B + idx) * uq[s];
       if constexpr (MODE == 2) {
-        const int32_t c = code[s];
+        const int32_t c = scode[q];
         if (c >= 0) {
           st_stream(acc, wf + c);
           ps[0] += (double)uq[s] * (double)acc;
