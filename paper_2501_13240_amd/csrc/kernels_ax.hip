@@ -556,11 +556,14 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
     }
   }
   if constexpr (MODE == 2) {
-    // one triple of sums per wavefront: no barrier, no LDS
+    // one triple of sums per wavefront: no barrier, no LDS.  Lane 0 is found
+    // by mbcnt here rather than from the lane index computed at the start,
+    // which the compiler would otherwise keep (and at N = 9 spill) all along.
+    const bool first_lane = __builtin_amdgcn_mbcnt_lo(~0u, 0u) == 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double x = wave_sum_d(ps[a]);
-      if (lane == 0) epart[(e * NW + wv) * 3 + a] = x;
+      if (first_lane) epart[(e * NW + wv) * 3 + a] = x;
     }
   }
 }
@@ -758,7 +761,12 @@ int ax_split_parts(int N) {
 }
 
 bool ax_split_available(const sem_mesh* m) {
-  if (!has_mfma(m->N) || !m->lmap2.p || !m->split_ok) return false;
+  // SEM_AX_SPLIT=0 (read once) keeps the gather form in the solve
+  static const bool enabled = [] {
+    const char* e = std::getenv("SEM_AX_SPLIT");
+    return !(e && std::strcmp(e, "0") == 0);
+  }();
+  if (!enabled || !has_mfma(m->N) || !m->lmap2.p || !m->split_ok) return false;
   const AxChoice c = ax_choice();
   return c == AxChoice::Auto ? prefer_mfma(m->N, true, false) : c == AxChoice::Mfma;
 }
