@@ -376,6 +376,18 @@ sem_status sem_advect(const sem_mesh* mesh, int32_t rule, const void* u, const v
 sem_status sem_advect_fields(const sem_mesh* mesh, int32_t rule, const void* u, int32_t nf,
                              const void* f, void* out, sem_prec prec, void* stream);
 
+/* Environment variables (read once per process; for comparisons, not needed
+ * in normal use):
+ *   SEM_AX_KERNEL=scalar|mfma   force the thread-per-point or the matrix-core
+ *                               element operator (default: matrix cores from
+ *                               N = 5 on);
+ *   SEM_AX_SPLIT=0              inside sem_pcg_solve, keep the gather form of
+ *                               the operator followed by a segmented sum over
+ *                               all free nodes (default from N = 5: single-copy
+ *                               nodes written by the operator directly);
+ *   SEM_GRAPH_MAX_FREE=n        largest solve (free nodes) that replays
+ *                               captured iteration graphs (default 262144). */
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* sem_last_error(void);
 
