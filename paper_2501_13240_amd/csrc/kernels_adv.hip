@@ -13,8 +13,11 @@
 // product (the M x (N+1) matrix J fits one tile, N <= 10), staged through
 // LDS; the last interpolation stage (along t) keeps its tile in registers,
 // where V and c are formed, so no M^3 array of u or of the derivatives is
-// ever stored.  The streaming of the factors (9 M^3 values against 5 (N+1)^3
-// of fields) bounds the kernel by HBM bandwidth.
+// ever stored.  The factors (9 M^3 values against 5 (N+1)^3 of fields) are
+// most of the HBM traffic.  With one field the kernel reaches about half of
+// the HBM peak: the factors of a pass can be requested only one pass ahead
+// within the register budget, less than the loaded latency.  With several
+// fields sharing V, it is bound by the matrix cores.
 //
 // Collocation (the GLL nodes themselves): one thread per node, derivative
 // sums over LDS.
