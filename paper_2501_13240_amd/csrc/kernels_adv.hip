@@ -88,7 +88,7 @@ constexpr int kAdvWaves = 4;
 constexpr int kAdvThreads = 64 * kAdvWaves;
 
 // The interpolation stages of an order-N element to M points per direction.
-template <int N, int M, typename T>
+template <int N, int M, typename T, int W = kAdvWaves>
 struct Stages {
   static constexpr int n = N + 1, P = n * n * n, Q = M * M * M;
   typedef Ct<T, n, n, n, M, 0> I0;  // (n,n,n) -> (n,n,M)
@@ -98,7 +98,7 @@ struct Stages {
   typedef Ct<T, n, M, M, n, 1> B1;  // (n,M,M) -> (n,n,M)
   typedef Ct<T, n, n, M, n, 0> B0;  // (n,n,M) -> (n,n,n)
   static constexpr int KN = I0::KS, KM = B2::KS;
-  static constexpr int TPW = (I2::NT + kAdvWaves - 1) / kAdvWaves;  // last-stage tiles per wave
+  static constexpr int TPW = (I2::NT + W - 1) / W;  // last-stage tiles per wave
   // LDS: the input block and the two first-stage outputs (later the M^3
   // array c and the (n,n,M) back-projection stage), and one (n,M,M) array
   static constexpr int IX = P + 2 * n * n * M;
@@ -106,12 +106,25 @@ struct Stages {
   static_assert(Q <= IX && P <= YS, "LDS regions");
 };
 
-// Tiles of a stage handled by this wavefront (t = wv, wv + 4, ...), unrolled.
+// Tiles of a stage handled by this wavefront (t = wv, wv + kW, ...), unrolled.
 #define FOR_TILES(C, ...)                                                               \
-  _Pragma("unroll") for (int ti_ = 0; ti_ < (C::NT + kAdvWaves - 1) / kAdvWaves; ++ti_) { \
-    const int t = wv + ti_ * kAdvWaves;                                                 \
+  _Pragma("unroll") for (int ti_ = 0; ti_ < (C::NT + kW - 1) / kW; ++ti_) {           \
+    const int t = wv + ti_ * kW;                                                        \
     if (t < C::NT) { __VA_ARGS__; }                                                     \
   }
+
+// Wavefronts per workgroup of the dealiased kernel: the faster of four and
+// eight, measured per order and precision on meshes of 14-16 thousand
+// elements.  Eight halve each wave's last-stage tiles, and with them its V
+// accumulators and prefetched factors: FP64 from N = 8 on then runs two waves
+// per SIMD instead of one (1.3-1.6x faster at N = 8..10), FP64 at N = 5, 6
+// gains 13-20 % and FP32 at N = 6 8 %.  FP64 at N = 7 and FP32 at the other
+// orders are faster with four waves, which keep two workgroups per CU; at
+// N <= 4 the stages have too few tiles for eight waves.
+template <int N, typename T>
+constexpr int adv_waves() {
+  return (sizeof(T) == 8 ? (N == 5 || N == 6 || N >= 8) : N == 6) ? 8 : kAdvWaves;
+}
 
 // Persistent: workgroup b processes elements b, b + grid, ...  The factors a
 // pass consumes are requested one pass ahead (the first pass's during the
@@ -120,11 +133,12 @@ struct Stages {
 // while the matrix cores interpolate.  V is formed once per element and
 // applied to each of the nf fields f[k] (stride E P, like u).
 template <int N, typename T>
-__global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
+__global__ __launch_bounds__((64 * adv_waves<N, T>())) void adv_dealias_kernel(
     int64_t E, int nf, const T* __restrict__ mats, const T* __restrict__ G,
     const T* __restrict__ u, int64_t ustride, const T* __restrict__ f, T* __restrict__ out) {
   constexpr int M = (3 * (N + 1)) / 2;
-  typedef Stages<N, M, T> S;
+  constexpr int kW = adv_waves<N, T>(), kThreads = 64 * kW;
+  typedef Stages<N, M, T, kW> S;
   typedef typename S::I0 I0;
   typedef typename S::I1 I1;
   typedef typename S::I2 I2;
@@ -157,7 +171,7 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
   int goff[TPW][4];
 #pragma unroll
   for (int ti = 0; ti < TPW; ++ti) {
-    const int t = wv + ti * kAdvWaves;
+    const int t = wv + ti * kW;
     const int col = t * 16 + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -180,7 +194,7 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
   if (e < E) fetch(e, 0);
   for (; e < E; e += gridDim.x) {
     const int64_t en = e + gridDim.x;
-    for (int q = threadIdx.x; q < 4 * P; q += kAdvThreads) {
+    for (int q = threadIdx.x; q < 4 * P; q += kThreads) {
       const int d = q / P, p = q - d * P;
       sIn[q] = d < 3 ? u[d * ustride + e * P + p] : f[e * P + p];
     }
@@ -200,7 +214,7 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
       __syncthreads();
 #pragma unroll
       for (int ti = 0; ti < TPW; ++ti) {
-        const int t = wv + ti * kAdvWaves;
+        const int t = wv + ti * kW;
         if (t < I2::NT) {
           const V ui = I2::tile(sY, aJ, t, lane);
 #pragma unroll
@@ -216,7 +230,7 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
     // every field k advected by the same V
     for (int k = 0; k < nf; ++k) {
       if (k > 0) {
-        for (int q = threadIdx.x; q < P; q += kAdvThreads)
+        for (int q = threadIdx.x; q < P; q += kThreads)
           sIn[3 * P + q] = f[k * ustride + e * P + q];
         __syncthreads();
       }
@@ -234,7 +248,7 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
         __syncthreads();
 #pragma unroll
         for (int ti = 0; ti < TPW; ++ti) {
-          const int t = wv + ti * kAdvWaves;
+          const int t = wv + ti * kW;
           if (t < I2::NT) {
             // one derivative tile live at a time (the scheduler would
             // otherwise hoist all of them and halve the occupancy)
@@ -259,7 +273,7 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
           __syncthreads();
 #pragma unroll
           for (int ti = 0; ti < TPW; ++ti) {
-            const int t = wv + ti * kAdvWaves;
+            const int t = wv + ti * kW;
             if (t < I2::NT) {
               const V fa = I2::tile(sY, a2, t, lane);
 #pragma unroll
@@ -273,7 +287,7 @@ __global__ __launch_bounds__(kAdvThreads) void adv_dealias_kernel(
       T* sC = sR;
 #pragma unroll
       for (int ti = 0; ti < TPW; ++ti) {
-        const int t = wv + ti * kAdvWaves;
+        const int t = wv + ti * kW;
         if (t < I2::NT) I2::store(sC, c[ti], t, lane);
       }
       __syncthreads();
@@ -427,7 +441,8 @@ hipError_t run_advect(const sem_mesh* m, int rule, int nf, const T* mats, const 
   // persistent grid: twice the resident workgroups (measured best of 1x, 2x)
   static const int per_cu = [] {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, adv_dealias_kernel<N, T>, kAdvThreads,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, adv_dealias_kernel<N, T>,
+                                                     64 * adv_waves<N, T>(),
                                                      0) != hipSuccess || v <= 0)
       v = 1;
     return v;
@@ -438,7 +453,7 @@ hipError_t run_advect(const sem_mesh* m, int rule, int nf, const T* mats, const 
   if (e != hipSuccess) return e;
   int64_t grid = 2 * (int64_t)cus * per_cu;
   if (grid > m->E) grid = m->E;
-  hipLaunchKernelGGL((adv_dealias_kernel<N, T>), dim3((unsigned)grid), dim3(kAdvThreads), 0, s,
+  hipLaunchKernelGGL((adv_dealias_kernel<N, T>), dim3((unsigned)grid), dim3(64 * adv_waves<N, T>()), 0, s,
                      m->E, nf, mats, G, u, ustride, f, out);
   return hipGetLastError();
 }
