@@ -65,7 +65,7 @@ def test_advect_fp64_matches_oracle(N, rule):
 
 
 @pytest.mark.parametrize("rule", list(RULES))
-@pytest.mark.parametrize("N", [3, 7, 9])
+@pytest.mark.parametrize("N", [3, 6, 7, 9])
 def test_advect_fp32_matches_oracle(N, rule):
     m, u, f = _case(N)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
@@ -162,7 +162,7 @@ def test_errors():
 
 
 @pytest.mark.parametrize("rule", list(RULES))
-@pytest.mark.parametrize("N", [2, 7, 9])
+@pytest.mark.parametrize("N", [2, 6, 7, 9])  # four- and eight-wave workgroups in both precisions
 def test_advect_fields_equals_one_field_calls_and_oracle(N, rule):
     # a Boussinesq step's four advected fields: T and the velocity components
     m, u, T = _case(N, shape=(3, 2, 4))
