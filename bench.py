@@ -451,13 +451,29 @@ def main():
     log("convective term (sem_advect) on the benchmark mesh ...")
     adv = advection_rate(sem, M, m, args.ax_reps)
 
+    # what a plain device copy sustains on this HBM (context for the fractions
+    # of the 8 TB/s peak above): 1 GiB read and 1 GiB written per copy
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(5)]
+    for e0, e1 in cev:
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+    torch.cuda.synchronize()
+    copy_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in cev]))
+    copy_gb_s = 2.0 * src.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    log(f"1 GiB device copy: {copy_ms * 1e3:.0f} us, {copy_gb_s:.0f} GB/s")
     if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
+        # three more dispatches, so the counter runs see the copy kernel at
+        # least three times whatever else the run launches
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 x 1 GiB device copies done")
+    del src, dst
 
     out = {
         "metric": "GDOF/s of SEM Ax and PCG solve (N=7, 1 GPU); mixed vs FP64 at 1e-10 residual",
@@ -496,6 +512,8 @@ def main():
         "ax_gdof_s": n_unique / (sem_ax_ms * 1e-3) / 1e9,
         "ax_us": sem_ax_ms * 1e3,
         "ax_hbm_frac": 64.0 * nL / (sem_ax_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "hbm_copy": {"gb_s": copy_gb_s, "frac_of_peak": copy_gb_s / PEAK_HBM_GBS,
+                     "what": "torch copy_ of 1 GiB FP64, device to device, median of 5"},
         "gs": gs,
         "advection": adv,
     }

@@ -159,9 +159,15 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
   block_partials<3>(v, part);
 }
 
+// What the residual vector of a CG iteration holds, and which partials the
+// update forms: r (and r.r only), r (r.r and r.S r, Jacobi), or z = S r in
+// place of r (Jacobi: r = z / S is recovered in registers, so the direction
+// update p = z + beta p reads neither r nor S)
+enum UpdMode { kUpdR = 0, kUpdJacR = 1, kUpdJacZ = 2 };
+
 // alpha from the p.w partials; x += alpha p;  r -= alpha (w - mean_w);
 // partials of r.r (and r.S r)
-template <typename T, bool JAC>
+template <typename T, int MODE>
 __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict__ x,
                                                       const T* __restrict__ p, T* __restrict__ r,
                                                       const T* __restrict__ w,
@@ -199,11 +205,20 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
   double v[2] = {0.0, 0.0};
   BLOCK_CHUNK(g, nf) {
     x[g] = x[g] + a * p[g];
-    const T rg = r[g] - a * (w[g] - mwt);
-    r[g] = rg;
-    const double rd = (double)rg;
-    v[0] += rd * rd;
-    if (JAC) v[1] += rd * rd * (double)dinv[g];
+    if constexpr (MODE == kUpdJacZ) {
+      const T d = dinv[g];
+      const T rg = r[g] / d - a * (w[g] - mwt);
+      const T zg = d * rg;
+      r[g] = zg;
+      v[0] += (double)rg * (double)rg;
+      v[1] += (double)rg * (double)zg;
+    } else {
+      const T rg = r[g] - a * (w[g] - mwt);
+      r[g] = rg;
+      const double rd = (double)rg;
+      v[0] += rd * rd;
+      if (MODE == kUpdJacR) v[1] += rd * rd * (double)dinv[g];
+    }
   }
   block_partials<2>(v, part);
 }
@@ -236,8 +251,8 @@ __device__ __forceinline__ bool cg_check(double rr, int kit, CgScalars* __restri
   return !stop;
 }
 
-// Jacobi: check, beta = r.S r / rho, p = S r + beta p
-template <typename T>
+// Jacobi: check, beta = r.S r / rho, p = S r + beta p (ZS: r holds z = S r)
+template <typename T, bool ZS>
 __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __restrict__ p,
                                                            const T* __restrict__ r,
                                                            const T* __restrict__ dinv,
@@ -258,7 +273,11 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __rest
     if (bhist) bhist[kit] = beta;
   }
   const T b = (T)beta;
-  BLOCK_CHUNK(g, nf) p[g] = dinv[g] * r[g] + b * p[g];
+  if constexpr (ZS) {
+    BLOCK_CHUNK(g, nf) p[g] = r[g] + b * p[g];
+  } else {
+    BLOCK_CHUNK(g, nf) p[g] = dinv[g] * r[g] + b * p[g];
+  }
 }
 
 // flexible CG: beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha z.(w - mean_w) / rho_k
@@ -335,18 +354,33 @@ __global__ __launch_bounds__(kVecBlock) void k_totals(const double* __restrict__
   if (threadIdx.x < NV) out[threadIdx.x] = S[threadIdx.x];
 }
 
-// p = S r (Jacobi) or p = z; partials of r.p
+// p = z; partials of r.p
 template <typename T>
 __global__ __launch_bounds__(kVecBlock) void k_init_p(int64_t nf, T* __restrict__ p,
                                                       const T* __restrict__ r,
-                                                      const T* __restrict__ dinv,
                                                       const T* __restrict__ z,
                                                       double* __restrict__ part) {
   double v[1] = {0.0};
   BLOCK_CHUNK(g, nf) {
-    const T pg = z ? z[g] : dinv[g] * r[g];
+    const T pg = z[g];
     p[g] = pg;
     v[0] += (double)pg * (double)r[g];
+  }
+  block_partials<1>(v, part);
+}
+
+// Jacobi with z kept in place of r: z = S r, p = z; partials of r.z
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_init_pz(int64_t nf, T* __restrict__ p,
+                                                       T* __restrict__ rz,
+                                                       const T* __restrict__ dinv,
+                                                       double* __restrict__ part) {
+  double v[1] = {0.0};
+  BLOCK_CHUNK(g, nf) {
+    const T rg = rz[g], zg = dinv[g] * rg;
+    p[g] = zg;
+    rz[g] = zg;
+    v[0] += (double)zg * (double)rg;
   }
   block_partials<1>(v, part);
 }
@@ -789,12 +823,12 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   }
 
   // z0 = M r0, p0 = z0, rho = r0.z0
+  // (Jacobi: from here on r holds z = S r; nothing reads r after the solve)
   if (jac) {
-    hipLaunchKernelGGL((k_init_p<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv,
-                       (const T*)nullptr, part);
+    hipLaunchKernelGGL((k_init_pz<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv, part);
   } else {
     if ((st = a.cheb(m, W, r, z, ChebCg(), s, &res.applies))) return st;
-    hipLaunchKernelGGL((k_init_p<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, a.dinv, z, part);
+    hipLaunchKernelGGL((k_init_p<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, z, part);
   }
   hipLaunchKernelGGL((k_totals<1>), dim3(1), dim3(kVecBlock), 0, s, part, (int)nb, W.red.as<double>());
   SEM_CHECK_LAUNCH("initial direction");
@@ -850,12 +884,12 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
                          m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, p, w, partA, sc);
     }
     if (jac) {
-      hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
-                         a.dinv, partA, (int)nb, partB, sc, ahist);
-      hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, r, a.dinv,
+      hipLaunchKernelGGL((k_update<T, kUpdJacZ>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r,
+                         w, a.dinv, partA, (int)nb, partB, sc, ahist);
+      hipLaunchKernelGGL((k_pupdate_jac<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, r, a.dinv,
                          partB, (int)nb, sc, hist, bhist);
     } else {
-      hipLaunchKernelGGL((k_update<T, false>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
+      hipLaunchKernelGGL((k_update<T, kUpdR>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
                          a.dinv, partA, (int)nb, partB, sc, ahist);
       ChebCg cg;
       cg.sc = sc;
@@ -1057,9 +1091,9 @@ sem_status cg_fixed_device(const sem_mesh* m, SolveWork& W, const Op<T>& op, con
     if (st) return st;
     hipLaunchKernelGGL((k_gsum_pw<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, m->fseg.as<int32_t>(),
                        m->fperm.as<int32_t>(), wL, p, w, partA, sc);
-    hipLaunchKernelGGL((k_update<T, true>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w, dinv,
+    hipLaunchKernelGGL((k_update<T, kUpdJacR>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w, dinv,
                        partA, (int)nb, partB, sc, (double*)nullptr);
-    hipLaunchKernelGGL((k_pupdate_jac<T>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, dinv, partB,
+    hipLaunchKernelGGL((k_pupdate_jac<T, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, dinv, partB,
                        (int)nb, sc, (double*)nullptr, (double*)nullptr);
   }
   SEM_CHECK_LAUNCH("coarse CG");
