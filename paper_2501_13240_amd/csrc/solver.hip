@@ -110,7 +110,9 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t
                                                        const T* __restrict__ wL,
                                                        const T* __restrict__ p, T* __restrict__ w,
                                                        double* __restrict__ part,
-                                                       const CgScalars* __restrict__ sc) {
+                                                       CgScalars* __restrict__ sc) {
+  // the previous iteration's direction update has completed
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->pending = 0;
   if (sc->done) return;
   double v[3] = {0.0, 0.0, 0.0};
   BLOCK_CHUNK(g, nf) {
@@ -133,8 +135,8 @@ template <typename T>
 __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
     int64_t n1, int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
     const T* __restrict__ wL, const T* __restrict__ p, T* __restrict__ w, int64_t ne,
-    const double* __restrict__ epart, double* __restrict__ part,
-    const CgScalars* __restrict__ sc) {
+    const double* __restrict__ epart, double* __restrict__ part, CgScalars* __restrict__ sc) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->pending = 0;
   if (sc->done) return;
   double v[3] = {0.0, 0.0, 0.0};
   {
@@ -162,7 +164,8 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
 // What the residual vector of a CG iteration holds, and which partials the
 // update forms: r (and r.r only), r (r.r and r.S r, Jacobi), or z = S r in
 // place of r (Jacobi: r = z / S is recovered in registers, so the direction
-// update p = z + beta p reads neither r nor S)
+// update p = z + beta p reads neither r nor S).  In the last mode x += alpha p
+// is left to the direction update, which reads p anyway.
 enum UpdMode { kUpdR = 0, kUpdJacR = 1, kUpdJacZ = 2 };
 
 // alpha from the p.w partials; x += alpha p;  r -= alpha (w - mean_w);
@@ -199,12 +202,12 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
     sc->alpha = alpha;
     sc->mean_w = mw;
     sc->kcur = kit;
+    if (MODE == kUpdJacZ) sc->pending = 1;
     if (ahist) ahist[kit] = alpha;
   }
   const T a = (T)alpha, mwt = (T)mw;
   double v[2] = {0.0, 0.0};
   BLOCK_CHUNK(g, nf) {
-    x[g] = x[g] + a * p[g];
     if constexpr (MODE == kUpdJacZ) {
       const T d = dinv[g];
       const T rg = r[g] / d - a * (w[g] - mwt);
@@ -213,6 +216,7 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
       v[0] += (double)rg * (double)rg;
       v[1] += (double)rg * (double)zg;
     } else {
+      x[g] = x[g] + a * p[g];
       const T rg = r[g] - a * (w[g] - mwt);
       r[g] = rg;
       const double rd = (double)rg;
@@ -251,22 +255,34 @@ __device__ __forceinline__ bool cg_check(double rr, int kit, CgScalars* __restri
   return !stop;
 }
 
-// Jacobi: check, beta = r.S r / rho, p = S r + beta p (ZS: r holds z = S r)
+// Jacobi: check, beta = r.S r / rho, p = S r + beta p.  ZS: r holds z = S r,
+// and x += alpha p (alpha of the update kernel) is applied here first, also
+// in the iteration that stops the solve.  The guard is then the pending flag,
+// which no block of this kernel writes (block 0 sets done while other blocks
+// may still be starting).
 template <typename T, bool ZS>
 __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __restrict__ p,
+                                                           T* __restrict__ x,
                                                            const T* __restrict__ r,
                                                            const T* __restrict__ dinv,
                                                            const double* __restrict__ part_in,
                                                            int nblk, CgScalars* __restrict__ sc,
                                                            double* __restrict__ hist,
                                                            double* __restrict__ bhist) {
-  if (sc->done) return;
+  if (ZS ? !sc->pending : sc->done) return;
   const int kit = sc->kcur;
+  const double rho = sc->rho2[kit & 1];
+  const T a = (T)sc->alpha;
   double S[2];
   block_total<2>(part_in, nblk, S);
-  if (!cg_check(S[0], kit, sc, hist)) return;
+  if (!cg_check(S[0], kit, sc, hist)) {
+    if constexpr (ZS) {
+      BLOCK_CHUNK(g, nf) x[g] = x[g] + a * p[g];
+    }
+    return;
+  }
   const double rz = S[1];
-  const double beta = rz / sc->rho2[kit & 1];
+  const double beta = rz / rho;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->rho2[(kit + 1) & 1] = rz;
     sc->beta = beta;
@@ -274,7 +290,11 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __rest
   }
   const T b = (T)beta;
   if constexpr (ZS) {
-    BLOCK_CHUNK(g, nf) p[g] = r[g] + b * p[g];
+    BLOCK_CHUNK(g, nf) {
+      const T pg = p[g];
+      x[g] = x[g] + a * pg;
+      p[g] = r[g] + b * pg;
+    }
   } else {
     BLOCK_CHUNK(g, nf) p[g] = dinv[g] * r[g] + b * p[g];
   }
@@ -886,8 +906,8 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
     if (jac) {
       hipLaunchKernelGGL((k_update<T, kUpdJacZ>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r,
                          w, a.dinv, partA, (int)nb, partB, sc, ahist);
-      hipLaunchKernelGGL((k_pupdate_jac<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, r, a.dinv,
-                         partB, (int)nb, sc, hist, bhist);
+      hipLaunchKernelGGL((k_pupdate_jac<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, x, r,
+                         a.dinv, partB, (int)nb, sc, hist, bhist);
     } else {
       hipLaunchKernelGGL((k_update<T, kUpdR>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
                          a.dinv, partA, (int)nb, partB, sc, ahist);
@@ -1093,8 +1113,8 @@ sem_status cg_fixed_device(const sem_mesh* m, SolveWork& W, const Op<T>& op, con
                        m->fperm.as<int32_t>(), wL, p, w, partA, sc);
     hipLaunchKernelGGL((k_update<T, kUpdJacR>), dim3(nb), dim3(kVecBlock), 0, s, nf, x, p, r, w, dinv,
                        partA, (int)nb, partB, sc, (double*)nullptr);
-    hipLaunchKernelGGL((k_pupdate_jac<T, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, r, dinv, partB,
-                       (int)nb, sc, (double*)nullptr, (double*)nullptr);
+    hipLaunchKernelGGL((k_pupdate_jac<T, false>), dim3(nb), dim3(kVecBlock), 0, s, nf, p, x, r, dinv,
+                       partB, (int)nb, sc, (double*)nullptr, (double*)nullptr);
   }
   SEM_CHECK_LAUNCH("coarse CG");
   return SEM_OK;

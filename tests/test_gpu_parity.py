@@ -303,6 +303,24 @@ def test_graph_replayed_solve_matches_eager_launches(precond):
     assert torch.equal(xf_e, xf_g)
 
 
+@pytest.mark.parametrize("profile", [False, True])  # graph replay / eager launches
+def test_stopped_solve_equals_fixed_solve_of_same_length(profile):
+    """A solve that stops on the tolerance applies its last x update exactly
+    once: the launches queued after the stop leave x alone, and x equals that
+    of a fixed-length solve of the same iteration count, bit for bit."""
+    m, fld = config_mesh(1, N=5)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    b = sem.gs(M, sem.mass(M, dev(fld["f"])))
+    for precond in ("jacobi", "chebyshev"):
+        x, st = sem.solve(M, b, precond=precond, rtol=1e-9, profile=profile)
+        n = st["iters"]
+        assert st["converged"] == 1
+        xf, stf = sem.solve(M, b, precond=precond, max_iter=n, fixed_iters=True,
+                            profile=profile)
+        assert stf["iters"] == n
+        assert torch.equal(x, xf), precond
+
+
 @pytest.mark.parametrize("precond_prec", ["fp64", "fp32"])
 def test_pcg_first_kind_chebyshev_matches_oracle(precond_prec):
     """The first-kind Chebyshev variant on [rho/10, rho] (same bound as the
