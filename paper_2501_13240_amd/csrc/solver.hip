@@ -8,8 +8,10 @@
 //   ax (gathers p through lmap, writes the element-local result w_L; from
 //   N = 5 on it writes w at the single-copy nodes directly, with their p.w)
 //   -> segmented sum w = R Q^T w_L fused with p.w (over the shared nodes)
-//   -> alpha on the device -> x, r update fused with r.r (and r.S r)
-//   -> beta on the device -> p update.
+//   -> alpha on the device -> residual update fused with r.r (and r.S r)
+//   -> beta on the device -> p update.  Jacobi keeps z = S r in place of r
+//   and applies x += alpha p in the p update; the other preconditioners
+//   update x with r.
 // All scalars stay on the device (CgScalars); the host only polls the `done`
 // flag every few iterations with one chunk of iterations always queued ahead,
 // and every kernel of a finished solve returns at once.  Reductions use a
@@ -168,8 +170,8 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
 // is left to the direction update, which reads p anyway.
 enum UpdMode { kUpdR = 0, kUpdJacR = 1, kUpdJacZ = 2 };
 
-// alpha from the p.w partials; x += alpha p;  r -= alpha (w - mean_w);
-// partials of r.r (and r.S r)
+// alpha from the p.w partials; x += alpha p (not kUpdJacZ);
+// r -= alpha (w - mean_w); partials of r.r (and r.S r)
 template <typename T, int MODE>
 __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict__ x,
                                                       const T* __restrict__ p, T* __restrict__ r,
