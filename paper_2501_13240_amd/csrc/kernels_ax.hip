@@ -9,9 +9,12 @@
 // -- u (or its gather through the free numbering), the six geometric factors
 // and k -- before the first barrier, so a workgroup has its whole element in
 // flight at once; the streamed arrays are read and w written with
-// nontemporal hints (each byte is touched once).  The element block and D
-// live in LDS; the reference-gradient phase and the transposed phase are
-// separated by one barrier.  For N = 7 a wavefront is exactly one k-plane,
+// nontemporal hints (each byte is touched once).  The in-solve form's
+// shared-copy outputs are plain stores instead: the segmented sum reads them
+// right after and finds most of them in the memory-side cache (its time per
+// iteration 28 -> 22 us, against 2 us more for the operator).  The element
+// block and D live in LDS; the reference-gradient phase and the transposed
+// phase are separated by one barrier.  For N = 7 a wavefront is exactly one k-plane,
 // so the t-direction coefficients D[k][l] are wave-uniform and come from
 // scalar loads instead of LDS.
 //
@@ -548,7 +551,7 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
           ps[2] += (double)uq[s];
         } else if (c <= -2) {
           // shared copy: at its surface slot of the element's block
-          st_stream(acc, w + e * P + surface_rank(q % n1, (q / n1) % n1, q / (n1 * n1), N));
+          w[e * P + surface_rank(q % n1, (q / n1) % n1, q / (n1 * n1), N)] = acc;
         }
       } else {
         st_stream(acc, w + idx);

@@ -211,7 +211,9 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
   double v[2] = {0.0, 0.0};
   BLOCK_CHUNK(g, nf) {
     if constexpr (MODE == kUpdJacZ) {
-      const T d = dinv[g];
+      // S and x (below) are touched once per iteration: nontemporal, so the
+      // memory-side cache keeps p, z and w, which are re-read a kernel later
+      const T d = __builtin_nontemporal_load(dinv + g);
       const T rg = r[g] / d - a * (w[g] - mwt);
       const T zg = d * rg;
       r[g] = zg;
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __rest
   if constexpr (ZS) {
     BLOCK_CHUNK(g, nf) {
       const T pg = p[g];
-      x[g] = x[g] + a * pg;
+      __builtin_nontemporal_store(__builtin_nontemporal_load(x + g) + a * pg, x + g);
       p[g] = r[g] + b * pg;
     }
   } else {
