@@ -354,8 +354,9 @@ struct MShape {
 // with one local copy, -(v + 2) for a shared free node v, -1 for a Dirichlet
 // copy; single-copy results go straight to the free vector wf[v], shared
 // copies' results to w (local, for the segmented sum), and epart[3 (NW e +
-// wave) + a] receives each wavefront's sums of p w, w and p over its
-// single-copy nodes (p = the gathered input), reduced in a fixed order.
+// wave) + a] receives each wavefront's sums of p w and w over all its free
+// copies and of p over its single-copy nodes (p = the gathered input),
+// reduced in a fixed order.
 // Waves per SIMD the split in-solve form asks for: the gather form's
 // occupancy at N = 6 and N = 9, which a few extra registers would cost it
 // (at N = 9, with 512-thread workgroups, one fewer resident workgroup per CU
@@ -550,8 +551,12 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
           ps[1] += (double)acc;
           ps[2] += (double)uq[s];
         } else if (c <= -2) {
-          // shared copy: at its surface slot of the element's block
+          // shared copy: at its surface slot of the element's block.  Its
+          // share of p.w and sum(w): over all copies these add up to p_g w_g
+          // and w_g (sum(p) over the shared nodes is left to the segmented sum)
           w[e * P + surface_rank(q % n1, (q / n1) % n1, q / (n1 * n1), N)] = acc;
+          ps[0] += (double)uq[s] * (double)acc;
+          ps[1] += (double)acc;
         }
       } else {
         st_stream(acc, w + idx);

@@ -129,10 +129,11 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t
 }
 
 // The same for the split operator, which has already written w at the
-// single-copy free nodes [0, n1) and their partial sums (ne triples, one per
-// wavefront of each element): segmented sums over the shared free nodes
-// [n1, nf) only, plus this block's chunk of the partial triples (in order,
-// so the totals stay deterministic).
+// single-copy free nodes [0, n1) and the partial sums (ne triples, one per
+// wavefront of each element; p.w and sum(w) over all copies, sum(p) over the
+// single-copy nodes): segmented sums over the shared free nodes [n1, nf)
+// only, plus this block's chunk of the partial triples (in order, so the
+// totals stay deterministic).
 template <typename T>
 __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
     int64_t n1, int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
@@ -151,14 +152,13 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
       v[2] += epart[3 * e + 2];
     }
   }
+  // the operator's triples already hold p.w and sum(w) over every copy;
+  // sum(p) over the shared nodes is needed for the null-space projection only
+  const bool sum_p = sc->neumann != 0;
   BLOCK_CHUNK(i, nf - n1) {
     const int64_t g = n1 + i;
-    const T s = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
-    w[g] = s;
-    const double pg = (double)p[g];
-    v[0] += pg * (double)s;
-    v[1] += (double)s;
-    v[2] += pg;
+    w[g] = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
+    if (sum_p) v[2] += (double)p[g];
   }
   block_partials<3>(v, part);
 }
