@@ -303,6 +303,29 @@ def test_graph_replayed_solve_matches_eager_launches(precond):
     assert torch.equal(xf_e, xf_g)
 
 
+def test_pcg_full_convection_box_true_residual():
+    """The benchmark's solve at full size (32x32x16 elements, N = 7: the split
+    in-solve operator and the Jacobi kernels that keep z in place of r, eager
+    launches).  Too large for the oracle, so: the true residual, formed with
+    the stand-alone operator (parity-tested against the oracle above), meets
+    the tolerance; a fixed solve of the same length gives the same x bit for
+    bit; copies of a node agree and Dirichlet copies are exact zeros."""
+    m, fld = config_mesh(2)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    b = dev(fld["b"])
+    x, st = sem.solve(M, b, rtol=1e-10)
+    r = sem.mask(M, (b - sem.gs(M, sem.ax(M, x))).contiguous())
+    mult = M.multiplicity()
+    bb = sem.mask(M, b.clone())
+    res = float(torch.sqrt(torch.sum(r * r / mult) / torch.sum(bb * bb / mult)))
+    print(f"convection box Jacobi PCG: {st['iters']} iterations, true res {res:.2e}")
+    assert st["converged"] == 1 and res <= 1.2e-10
+    xf, stf = sem.solve(M, b, max_iter=st["iters"], fixed_iters=True)
+    assert torch.equal(x, xf)
+    assert float((sem.gs(M, x.clone()) / mult - x).abs().max()) <= 1e-15 * float(x.abs().max())
+    assert int(torch.count_nonzero(x[torch.as_tensor(m.dirichlet != 0, device="cuda")])) == 0
+
+
 @pytest.mark.parametrize("profile", [False, True])  # graph replay / eager launches
 def test_stopped_solve_equals_fixed_solve_of_same_length(profile):
     """A solve that stops on the tolerance applies its last x update exactly
