@@ -189,8 +189,9 @@ def test_pcg_fixed_iterations_periodic_box_histories_agree():
     assert rel(P.num.from_local_consistent(x.cpu().numpy()), ref["x"]) <= 1e-8
 
 
-def test_pcg_neumann_matches_oracle():
-    m, fld = config_mesh(5, N=4, shape=(4, 4, 4))
+@pytest.mark.parametrize("N", [4, 7])  # gather-form and split in-solve operator
+def test_pcg_neumann_matches_oracle(N):
+    m, fld = config_mesh(5, N=N, shape=(4, 4, 4))
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
     P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
     b_or = P.num.from_local_consistent(fld["b"])
