@@ -7,10 +7,10 @@
  * nodes and quadrature, unknowns ordered as tensors (ijk, i fastest) on the
  * reference cube [-1,1]^3, operators applied matrix-free as dense
  * (N+1)x(N+1) contractions identical for all elements and carried to deformed
- * elements by the chain rule.  The pressure Poisson solve is the stiffest part
+ * elements by the chain rule.  The pressure Poisson solve is the hardest part
  * of each time step and is solved by preconditioned conjugate gradients
- * (Sec. 2.2), with fourth-kind Chebyshev acceleration and FP32 preconditioner
- * work "to save on memory bandwidth" (Sec. 2.2).
+ * (Sec. 2.2), with fourth-kind Chebyshev acceleration and preconditioner work
+ * in FP32, which halves its memory traffic (Sec. 2.2).
  *
  * Notation used below:
  *   P   = (N+1)^3 local points per element, local index q = i + (N+1)(j + (N+1)k)
