@@ -124,6 +124,29 @@ def test_full_size_convection_box_sampled():
             assert relmax(many[k].cpu().numpy(), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("N", [5, 6, 8, 9, 10])
+def test_dealias_persistent_grid_sampled(N):
+    # 1280 elements: more than the persistent grid, so workgroups walk
+    # several elements and prefetch the next one's factors (the small meshes
+    # above give every workgroup a single element)
+    m, _ = config_mesh(2, N=N, shape=(16, 16, 5))
+    u = velocity_field(m.xyz, seed=11, M=8)
+    f = random_fourier_field(m.xyz, seed=7, M=8)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, N)
+    idx = np.sort(np.random.default_rng(N).choice(m.E, 12, replace=False))
+    idx[-1] = m.E - 1
+    sel = torch.as_tensor(idx, device="cuda")
+    ref = convect(np.moveaxis(u[:, idx], 0, 2), f[idx], m.xyz[idx], N, dealias=True)
+    fields = np.concatenate([f[None], u])
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 2e-5)):
+        out = sem.advect(M, dev(u, dt), dev(f, dt), rule="dealias")[sel]
+        assert relmax(out.double().cpu().numpy(), ref) <= tol, dt
+        many = sem.advect(M, dev(u, dt), dev(fields, dt), rule="dealias")[:, sel]
+        assert relmax(many[0].double().cpu().numpy(), ref) <= tol, dt
+        ref3 = convect(np.moveaxis(u[:, idx], 0, 2), u[2, idx], m.xyz[idx], N, dealias=True)
+        assert relmax(many[3].double().cpu().numpy(), ref3) <= tol, dt
+
+
 def test_errors():
     N = 3
     m, u, f = _case(N)
