@@ -170,6 +170,15 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
 // is left to the direction update, which reads p anyway.
 enum UpdMode { kUpdR = 0, kUpdJacR = 1, kUpdJacZ = 2 };
 
+// The Jacobi p update walks pairs of consecutive elements (one 16-byte access
+// per lane in FP64: 1.5 % faster per iteration than 8-byte accesses; the same
+// in the residual update was 0.3 % slower) when its vectors are 16-byte
+// aligned, as they are when each starts an allocation; else one element at a
+// time.  BLOCK_CHUNK over the nf / 2 pairs, the odd last element by one thread.
+__device__ __forceinline__ bool aligned16(const void* a, const void* b, const void* c) {
+  return (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) == 0;
+}
+
 // alpha from the p.w partials; x += alpha p (not kUpdJacZ);
 // r -= alpha (w - mean_w); partials of r.r (and r.S r)
 template <typename T, int MODE>
@@ -209,17 +218,19 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
   }
   const T a = (T)alpha, mwt = (T)mw;
   double v[2] = {0.0, 0.0};
-  BLOCK_CHUNK(g, nf) {
-    if constexpr (MODE == kUpdJacZ) {
-      // S and x (below) are touched once per iteration: nontemporal, so the
-      // memory-side cache keeps p, z and w, which are re-read a kernel later
+  if constexpr (MODE == kUpdJacZ) {
+    // S and x (in the p update) are touched once per iteration: nontemporal,
+    // so the memory-side cache keeps p, z and w, which are re-read a kernel later
+    BLOCK_CHUNK(g, nf) {
       const T d = __builtin_nontemporal_load(dinv + g);
       const T rg = r[g] / d - a * (w[g] - mwt);
       const T zg = d * rg;
       r[g] = zg;
       v[0] += (double)rg * (double)rg;
       v[1] += (double)rg * (double)zg;
-    } else {
+    }
+  } else {
+    BLOCK_CHUNK(g, nf) {
       x[g] = x[g] + a * p[g];
       const T rg = r[g] - a * (w[g] - mwt);
       r[g] = rg;
@@ -294,10 +305,27 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __rest
   }
   const T b = (T)beta;
   if constexpr (ZS) {
-    BLOCK_CHUNK(g, nf) {
-      const T pg = p[g];
-      __builtin_nontemporal_store(__builtin_nontemporal_load(x + g) + a * pg, x + g);
-      p[g] = r[g] + b * pg;
+    if (aligned16(p, x, r)) {
+      typedef T V2 __attribute__((ext_vector_type(2)));
+      V2* p2 = reinterpret_cast<V2*>(p);
+      V2* x2 = reinterpret_cast<V2*>(x);
+      const V2* z2 = reinterpret_cast<const V2*>(r);
+      BLOCK_CHUNK(h, nf / 2) {
+        const V2 pg = p2[h];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(x2 + h) + a * pg, x2 + h);
+        p2[h] = z2[h] + b * pg;
+      }
+      if ((nf & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const T pg = p[nf - 1];
+        x[nf - 1] = x[nf - 1] + a * pg;
+        p[nf - 1] = r[nf - 1] + b * pg;
+      }
+    } else {
+      BLOCK_CHUNK(g, nf) {
+        const T pg = p[g];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(x + g) + a * pg, x + g);
+        p[g] = r[g] + b * pg;
+      }
     }
   } else {
     BLOCK_CHUNK(g, nf) p[g] = dinv[g] * r[g] + b * p[g];
