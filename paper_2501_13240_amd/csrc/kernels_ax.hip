@@ -10,9 +10,10 @@
 // and k -- before the first barrier, so a workgroup has its whole element in
 // flight at once; the streamed arrays are read and w written with
 // nontemporal hints (each byte is touched once).  The in-solve form's
-// shared-copy outputs are plain stores instead: the segmented sum reads them
-// right after and finds most of them in the memory-side cache (its time per
-// iteration 28 -> 22 us, against 2 us more for the operator).  The element
+// shared-copy outputs are plain stores instead when the local array is small
+// enough: the segmented sum reads them right after and finds most of them in
+// the memory-side cache (28 -> 22 us per iteration on the 32x32x16, N = 7
+// box, against 2 us more for the operator).  The element
 // block and D live in LDS; the reference-gradient phase and the transposed
 // phase are separated by one barrier.  For N = 7 a wavefront is exactly one k-plane,
 // so the t-direction coefficients D[k][l] are wave-uniform and come from
@@ -356,7 +357,8 @@ struct MShape {
 // copies' results to w (local, for the segmented sum), and epart[3 (NW e +
 // wave) + a] receives each wavefront's sums of p w and w over all its free
 // copies and of p over its single-copy nodes (p = the gathered input),
-// reduced in a fixed order.
+// reduced in a fixed order.  MODE 3: MODE 2 with nontemporal shared-copy
+// stores (for local arrays larger than the memory-side cache).
 // Waves per SIMD the split in-solve form asks for: the gather form's
 // occupancy at N = 6 and N = 9, which a few extra registers would cost it
 // (at N = 9, with 512-thread workgroups, one fewer resident workgroup per CU
@@ -365,7 +367,7 @@ constexpr int split_min_waves(int N) { return N == 6 ? 7 : N == 9 ? 6 : 1; }
 
 template <int N, typename T, int MODE, int LP>
 __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
-    amdgpu_waves_per_eu(MODE == 2 && sizeof(T) == 8 ? split_min_waves(N) : 1))) void ax_mfma_kernel(
+    amdgpu_waves_per_eu(MODE >= 2 && sizeof(T) == 8 ? split_min_waves(N) : 1))) void ax_mfma_kernel(
     const T* __restrict__ u, const int32_t* __restrict__ lmap, T* __restrict__ w,
     const T* __restrict__ kf, const T h2, const T* __restrict__ G, const T* __restrict__ B,
     const T* __restrict__ D, const int64_t E, const int32_t* __restrict__ skip,
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
   T uq[PPT], gq[PPT][6], kq[PPT];
   // MODE 2: each point's routing code, kept in LDS until the stores (in
   // registers it cost the N = 9 kernel a wave per SIMD)
-  __shared__ int32_t scode[MODE == 2 ? P : 1];
+  __shared__ int32_t scode[MODE >= 2 ? P : 1];
   // MODE >= 1: every routing code of this thread first, then the gathers
   // through them (0.6 % faster in-solve and p-multigrid iterations)
   int32_t lvq[PPT];
@@ -408,8 +410,8 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
     const int64_t idx = e * P + q;
     if constexpr (MODE >= 1) {
       const int32_t lv = lvq[s];
-      const int32_t lm = MODE == 2 ? (lv >= 0 ? lv : lv <= -2 ? -(lv + 2) : -1) : lv;
-      if constexpr (MODE == 2)
+      const int32_t lm = MODE >= 2 ? (lv >= 0 ? lv : lv <= -2 ? -(lv + 2) : -1) : lv;
+      if constexpr (MODE >= 2)
         if (qr < P) scode[qr] = lv;
       const T v = u[lm >= 0 ? lm : 0];
       uq[s] = lm >= 0 ? v : T(0);
@@ -554,7 +556,7 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
       const int64_t idx = e * P + q;
       T acc = so[q];
       if (use_h2) acc += h2 * ld_stream(B + idx) * uq[s];
-      if constexpr (MODE == 2) {
+      if constexpr (MODE >= 2) {
         const int32_t c = scode[q];
         if (c >= 0) {
           st_stream(acc, wf + c);
@@ -565,7 +567,11 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
           // shared copy: at its surface slot of the element's block.  Its
           // share of p.w and sum(w): over all copies these add up to p_g w_g
           // and w_g (sum(p) over the shared nodes is left to the segmented sum)
-          w[e * P + surface_rank(q % n1, (q / n1) % n1, q / (n1 * n1), N)] = acc;
+          T* dst = w + e * P + surface_rank(q % n1, (q / n1) % n1, q / (n1 * n1), N);
+          if constexpr (MODE == 2)
+            *dst = acc;
+          else
+            st_stream(acc, dst);
           ps[0] += (double)uq[s] * (double)acc;
           ps[1] += (double)acc;
         }
@@ -574,7 +580,7 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
       }
     }
   }
-  if constexpr (MODE == 2) {
+  if constexpr (MODE >= 2) {
     // one triple of sums per wavefront: no barrier, no LDS.  Lane 0 is found
     // by mbcnt here rather than from the lane index computed at the start,
     // which the compiler would otherwise keep (and at N = 9 spill) all along.
@@ -758,8 +764,18 @@ hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epa
                         const int32_t* skip) {
   if constexpr (has_mfma(N)) {
     using M = MShape<N>;
-    hipLaunchKernelGGL((ax_mfma_kernel<N, T, 2, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s, u,
-                       m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+    // shared-copy results stay in the memory-side cache for the segmented
+    // sum when the local array fits well inside it (256 MB): plain stores up
+    // to 128 MB (the 32x32x16, N = 7 box: 67 MB, 1.1 % faster per
+    // iteration), nontemporal above (the 32^3, N = 9 cube: 262 MB, 2.2 %)
+    // (MODE 2 plain, MODE 3 nontemporal: a run-time switch in the kernel cost
+    // what the nontemporal stores save)
+    if (m->nL * (int64_t)sizeof(T) <= (int64_t(128) << 20))
+      hipLaunchKernelGGL((ax_mfma_kernel<N, T, 2, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                         u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+    else
+      hipLaunchKernelGGL((ax_mfma_kernel<N, T, 3, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                         u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
     return hipGetLastError();
   } else {
     return hipErrorNotSupported;
