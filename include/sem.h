@@ -324,7 +324,7 @@ sem_status sem_host_coarse_mesh(int32_t N, int64_t E, const int64_t* gid,
                                 int64_t* gid_c, uint8_t* dirichlet_c, double* xyz_c);
 
 /* ------------------------------------------------------ convective term
- * The advection term u . grad f of the Boussinesq equations (Sec. 2.3: the
+ * The advection term u . grad f of the Boussinesq equations (Sec. 4.1: the
  * temperature and each velocity component are advected by the velocity), in
  * weak form per element:
  *   C_e(u) f |_i = sum_q phi_i(x_q) w_q detJ_q u(x_q) . grad f(x_q),

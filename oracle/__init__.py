@@ -26,7 +26,7 @@ definitions in order:
 * ``schwarz``   the overlapping Schwarz smoother with fast-diagonalisation
                 local solves that the p-multigrid cycle can accelerate;
 * ``advection`` the convective term u . grad T of the Boussinesq equations
-                (Sec. 2.3), by GLL collocation or by the 3/2 Gauss rule.
+                (Sec. 4.1), by GLL collocation or by the 3/2 Gauss rule.
 
 The paper names the method but prints none of its formulas; every function
 states the textbook definition it follows and each is pinned by a test under

@@ -3,7 +3,7 @@ over-integration (dealiasing).
 
 Test infrastructure only (see the package docstring).
 
-The Boussinesq equations of Sec. 2.3 carry the advection term u . grad T (and
+The Boussinesq equations of Sec. 4.1 carry the advection term u . grad T (and
 u . grad u).  The paper prints no discretisation for it; the reading taken
 here is the weak form on each element,
 

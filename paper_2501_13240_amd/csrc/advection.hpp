@@ -1,6 +1,6 @@
 // Convective term of the Boussinesq equations (internal): the element
 // contributions C_e(u) f = sum_q phi_i w_q detJ_q u(x_q) . grad f(x_q) of
-// the advection of temperature and velocity (Sec. 2.3), on the GLL nodes
+// the advection of temperature and velocity (Sec. 4.1), on the GLL nodes
 // (collocation) or on floor(3(N+1)/2) Gauss-Legendre points per direction
 // (over-integration, the 3/2 rule).
 #pragma once

@@ -1,4 +1,5 @@
-// Convective term C_e(u) f on every element (the advection of Sec. 2.3).
+// Convective term C_e(u) f on every element (the advection terms of the
+// Boussinesq equations, Sec. 4.1).
 //
 // Over-integrated rule (M = floor(3(N+1)/2) Gauss points per direction), one
 // element at a time per workgroup of four wavefronts:
@@ -22,7 +23,7 @@
 // Collocation (the GLL nodes themselves): one thread per node, derivative
 // sums over LDS.
 #include "advection.hpp"
-#include "mfma16.hpp"
+#include "mfma_16x16x4.hpp"
 
 namespace sem {
 namespace {

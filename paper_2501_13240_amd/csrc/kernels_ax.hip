@@ -39,6 +39,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "mfma_16x16x4.hpp"
 
 namespace sem {
 namespace {
@@ -182,31 +183,6 @@ __global__ __launch_bounds__(Shape<N>::BT) void ax_kernel(
 
 // ------------------------------------------------------------ matrix cores
 
-typedef double v4d_t __attribute__((ext_vector_type(4)));
-typedef float v4f_t __attribute__((ext_vector_type(4)));
-
-// 16x16x4 MFMA: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; result
-// element (i, j) in lane 16 (i % 4) + j, register i / 4 for FP64 and in lane
-// 16 (i / 4) + j, register i % 4 for FP32 (checked on the device).
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef v4d_t V;
-  static __device__ __forceinline__ V mma(double a, double b, V c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-template <>
-struct Mfma<float> {
-  typedef v4f_t V;
-  static __device__ __forceinline__ V mma(float a, float b, V c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-
 // One 16-column tile of a contraction along direction DIR of the element
 // block src ([k][j][i], n1 per direction): out[.., row, ..] = sum_l A[row][l]
 // src[.., l, ..], A = D (forward) or D^T (transposed), given as per-lane
@@ -221,7 +197,7 @@ __device__ __forceinline__ void contract_tile(const T* __restrict__ src, T* __re
   const int kk = lane >> 4;
   const bool cval = col < P2;
   const int c1 = cval ? col / n1 : 0, c0 = cval ? col % n1 : 0;
-  typename Mfma<T>::V acc = {T(0), T(0), T(0), T(0)};
+  typename Mm<T>::V acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     const int l = 4 * s + kk;
@@ -230,11 +206,11 @@ __device__ __forceinline__ void contract_tile(const T* __restrict__ src, T* __re
       const int a = DIR == 0 ? c1 * P2 + c0 * n1 + l : DIR == 1 ? c1 * P2 + l * n1 + c0 : l * P2 + col;
       b = src[a];
     }
-    acc = Mfma<T>::mma(afrag[s], b, acc);
+    acc = Mm<T>::mma(afrag[s], b, acc);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int row = Mfma<T>::row(lane, r);
+    const int row = Mm<T>::row(lane, r);
     if (cval && row < n1) {
       const int a =
           DIR == 0 ? c1 * P2 + c0 * n1 + row : DIR == 1 ? c1 * P2 + row * n1 + c0 : row * P2 + col;

@@ -8,7 +8,7 @@
 // free node completes z = sum_e R_e^T A~_e^{-1} R_e r.  Each 1-D transform of
 // the box is a batch of 16-column tiles C = M X on the matrix cores (16x16x4
 // MFMA in FP64 or FP32) with M = S or S^T of this element, read from LDS.
-#include "mfma16.hpp"
+#include "mfma_16x16x4.hpp"
 #include "schwarz.hpp"
 
 namespace sem {

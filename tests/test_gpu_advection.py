@@ -16,7 +16,8 @@ import pytest
 import torch
 
 from oracle.advection import convect, dealias_points, geometric_factors_q
-from sem_inputs import box_mesh, config_mesh, random_fourier_field, velocity_field
+from sem_inputs import (box_mesh, config_mesh, random_fourier_field, reference_node_placement,
+                        velocity_field)
 
 pytestmark = pytest.mark.gpu
 
@@ -225,3 +226,35 @@ def test_advect_fields_arguments():
     assert lib.sem_advect_fields(M.handle, 1, ptr(ud), 2, ptr(fd), ptr(out), 0, s) == L.SEM_OK
     torch.cuda.synchronize()
     assert torch.allclose(out[1], 2 * out[0], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("rule", list(RULES))
+@pytest.mark.parametrize("N", [4, 7])
+def test_advect_matches_oracle_on_sheared_affine_elements(N, rule):
+    """Separate affine elements x = c + M r with full, non-symmetric M
+    (rotated and sheared): the metric dr_a/dx_d has no zero entry, so an
+    index mistake in the kernel's factors or their use would show."""
+    rng = np.random.default_rng(40 + N)
+    xi = reference_node_placement(N)
+    k, j, i = np.meshgrid(xi, xi, xi, indexing="ij")
+    r = np.stack([i.ravel(), j.ravel(), k.ravel()], -1)
+    E = 6
+    xyz = np.empty((E, r.shape[0], 3))
+    for e in range(E):
+        Q, R = np.linalg.qr(rng.standard_normal((3, 3)))
+        Q = Q * np.sign(np.diag(R))
+        if np.linalg.det(Q) < 0:
+            Q[:, 0] = -Q[:, 0]
+        S = np.diag(rng.uniform(0.3, 0.7, 3))
+        S[0, 1], S[0, 2], S[1, 2] = rng.uniform(-0.25, 0.25, 3)
+        xyz[e] = rng.uniform(-1, 1, 3) + r @ (Q @ S).T
+    gid = np.arange(E * r.shape[0], dtype=np.int64).reshape(E, -1)
+    u = rng.standard_normal((3, E, r.shape[0]))
+    f = rng.standard_normal((E, r.shape[0]))
+    M = sem.Mesh(xyz, gid, None, N)
+    M.setup_advection(rule)
+    G = M.advection_factors(rule).cpu().numpy()
+    assert relmax(G, geometric_factors_q(xyz, N, RULES[rule]).reshape(E, 9, -1)) <= 1e-12
+    out = sem.advect(M, dev(u), dev(f), rule=rule).cpu().numpy()
+    ref = convect(np.moveaxis(u, 0, 2), f, xyz, N, dealias=RULES[rule])
+    assert relmax(out, ref) <= 1e-12

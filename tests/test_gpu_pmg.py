@@ -62,7 +62,8 @@ def _vcycle_case(m, N, k=None, h2=0.0, seed=1, smoother="jacobi"):
     e64, e32 = rel(z64, z_or), rel(z32, z_or)
     print(f"N={N} {smoother} levels {orders} rho {np.round(rho, 3)}: V-cycle fp64 {e64:.2e}, "
           f"fp32 {e32:.2e}")
-    assert e64 <= 1e-9
+    # FP64: the same arithmetic in another order (measured 2e-15 .. 2e-14)
+    assert e64 <= 1e-12
     assert e32 <= 2e-4
     return M, pmg, rho
 
