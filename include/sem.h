@@ -235,6 +235,26 @@ sem_status sem_pcg_solve(const sem_mesh* mesh, const double* b, double* x, const
                          double h2, const sem_solve_opts* opts, sem_solve_stats* stats,
                          void* stream);
 
+/* Backward of the solve x = A(k)^-1 b of sem_pcg_solve (the pressure /
+ * Helmholtz solve of Sec. 2.2) for a cotangent xbar of its copy-consistent
+ * local output x.  With lambda the solution of the adjoint system
+ * A(k) lambda = R Q^T xbar (A is symmetric: the same solve, run with `opts`
+ * from zero; with no Dirichlet node and h2 = 0 the constant mode is removed
+ * from the adjoint right-hand side and from lambda, as in the forward solve):
+ *   kbar_q = dL/dk_q = -sum_ab (D_a lambda_L)_q G_ab,q (D_b x)_q   if kbar != NULL
+ *   bbar_q = dL/db_q = lambda_L,q / (copies of q's node)          if bbar != NULL
+ * (lambda_L = lambda at every local copy, 0 at Dirichlet copies; the second
+ * line is the transpose of reading b as the mean of its copies).  x: the
+ * forward solution (DEVICE double [E][P], needed for kbar, else nullable);
+ * xbar, kbar, bbar: DEVICE double [E][P]; kbar and bbar must not alias x or
+ * each other; k, h2 as in the forward solve.  At least one of kbar, bbar.
+ * Blocks like sem_pcg_solve; stats (nullable) describe the adjoint solve.
+ * SEM_ENOCONV / SEM_EBREAKDOWN: the outputs are formed from the last
+ * adjoint iterate. */
+sem_status sem_solve_backward(const sem_mesh* mesh, const double* x, const double* xbar,
+                              const double* k, double h2, const sem_solve_opts* opts,
+                              double* kbar, double* bbar, sem_solve_stats* stats, void* stream);
+
 /* Backward of w = A_L(k) u for a cotangent wbar (all DEVICE double [E][P]):
  *   ubar = A_L(k) wbar                (A_L is symmetric)           if ubar != NULL
  *   kbar_q = sum_ab (D_a wbar)_q G_ab,q (D_b u)_q                   if kbar != NULL
@@ -386,7 +406,12 @@ sem_status sem_advect_fields(const sem_mesh* mesh, int32_t rule, const void* u, 
  *                               all free nodes (default from N = 5: single-copy
  *                               nodes written by the operator directly);
  *   SEM_GRAPH_MAX_FREE=n        largest solve (free nodes) that replays
- *                               captured iteration graphs (default 262144). */
+ *                               captured iteration graphs (default 262144);
+ *   SEM_AX_NT_BYTES=n           read at sem_setup_mesh: inside sem_pcg_solve
+ *                               the operator stores shared-copy results with
+ *                               nontemporal stores when the local array
+ *                               (E (N+1)^3 values) is larger than n bytes
+ *                               (default 134217728; 0 = always). */
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* sem_last_error(void);

@@ -28,6 +28,7 @@ from .api import (
     mass,
     pmg_apply,
     solve,
+    solve_backward,
 )
 from .autograd import SemSolve, sem_solve
 
@@ -55,6 +56,7 @@ __all__ = [
     "mass",
     "pmg_apply",
     "solve",
+    "solve_backward",
     "SemSolve",
     "sem_solve",
 ]

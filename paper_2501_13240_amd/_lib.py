@@ -101,6 +101,9 @@ SIGNATURES = {
                                 ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), c_void_p]),
     "sem_ax_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
                                   c_void_p, c_void_p]),
+    "sem_solve_backward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                     ctypes.POINTER(SolveOpts), c_void_p, c_void_p,
+                                     ctypes.POINTER(SolveStats), c_void_p]),
     "sem_last_error": (c_char_p, []),
 }
 

@@ -336,23 +336,9 @@ def lmax_estimate(mesh: Mesh, k=None, h2: float = 0.0, steps: int = 20) -> float
     return out.value
 
 
-def solve(mesh: Mesh, b, x0=None, k=None, h2: float = 0.0, *, mode: str = "cg",
-          precond: str = "jacobi", precond_prec: str | None = None, cheb_order: int = 3,
-          lmax: float = 0.0, rtol: float = 1e-10, max_iter: int = 10000,
-          fixed_iters: bool = False, inner_rtol: float = 1e-5, max_outer: int = 30,
-          check_every: int = 0, profile: bool = False, history: bool = False,
-          raise_on_noconv: bool = True, out=None):
-    """Solve A(k) x = b (sem_pcg_solve).  Returns (x, stats dict)."""
-    mesh.check_local(b, torch.float64, "b")
-    mesh.check_local(k, torch.float64, "k")
-    if out is None:
-        x = torch.zeros_like(b) if x0 is None else x0.clone()
-    else:
-        x = mesh.check_local(out, torch.float64, "out")
-        if x0 is None:
-            x.zero_()
-        else:
-            x.copy_(x0)
+def _solve_opts(mesh, mode, precond, precond_prec, cheb_order, lmax, rtol, max_iter,
+                fixed_iters, inner_rtol, max_outer, check_every, profile, history):
+    """sem_solve_opts from keyword arguments (and the residual-history buffer)."""
     if precond_prec is None:  # the multigrid cycle and the inner solve of refinement: FP32
         precond_prec = "fp32" if (precond == "pmg" or mode == "mixed_ir") else "fp64"
     if precond == "pmg" and not mesh._pmg:
@@ -375,17 +361,69 @@ def solve(mesh: Mesh, b, x0=None, k=None, h2: float = 0.0, *, mode: str = "cg",
     if history:
         hist = np.zeros(max_iter + 1)
         opts.residual_history = _np_ptr(hist)
-    st = L.SolveStats()
-    status = mesh._lib.sem_pcg_solve(mesh.handle, _ptr(b), _ptr(x), _ptr(k), float(h2),
-                                     ctypes.byref(opts), ctypes.byref(st), _stream())
+    return opts, hist
+
+
+def _stats_dict(st, status, hist):
     stats = {f: getattr(st, f) for f, _ in L.SolveStats._fields_ if f != "pad_"}
     stats["status"] = L.STATUS_NAMES.get(status, str(status))
     if hist is not None:
         stats["history"] = hist[: (stats["iters"] + 1)]
+    return stats
+
+
+def solve(mesh: Mesh, b, x0=None, k=None, h2: float = 0.0, *, mode: str = "cg",
+          precond: str = "jacobi", precond_prec: str | None = None, cheb_order: int = 3,
+          lmax: float = 0.0, rtol: float = 1e-10, max_iter: int = 10000,
+          fixed_iters: bool = False, inner_rtol: float = 1e-5, max_outer: int = 30,
+          check_every: int = 0, profile: bool = False, history: bool = False,
+          raise_on_noconv: bool = True, out=None):
+    """Solve A(k) x = b (sem_pcg_solve).  Returns (x, stats dict)."""
+    mesh.check_local(b, torch.float64, "b")
+    mesh.check_local(k, torch.float64, "k")
+    if out is None:
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+    else:
+        x = mesh.check_local(out, torch.float64, "out")
+        if x0 is None:
+            x.zero_()
+        else:
+            x.copy_(x0)
+    opts, hist = _solve_opts(mesh, mode, precond, precond_prec, cheb_order, lmax, rtol, max_iter,
+                             fixed_iters, inner_rtol, max_outer, check_every, profile, history)
+    st = L.SolveStats()
+    status = mesh._lib.sem_pcg_solve(mesh.handle, _ptr(b), _ptr(x), _ptr(k), float(h2),
+                                     ctypes.byref(opts), ctypes.byref(st), _stream())
+    stats = _stats_dict(st, status, hist)
     if status == L.SEM_ENOCONV and not raise_on_noconv:
         return x, stats
     _check(status, "sem_pcg_solve")
     return x, stats
+
+
+def solve_backward(mesh: Mesh, x, xbar, k=None, h2: float = 0.0, *, need_kbar: bool = True,
+                   need_bbar: bool = True, mode: str = "cg", precond: str = "jacobi",
+                   precond_prec: str | None = None, cheb_order: int = 3, lmax: float = 0.0,
+                   rtol: float = 1e-10, max_iter: int = 10000, inner_rtol: float = 1e-5,
+                   max_outer: int = 30, check_every: int = 0):
+    """(kbar, bbar, stats): the gradients dL/dk and dL/db of the solve
+    x = A(k)^-1 b for the cotangent xbar = dL/dx (sem_solve_backward; the
+    adjoint solve takes the same options as sem_pcg_solve)."""
+    mesh.check_local(x, torch.float64, "x")
+    mesh.check_local(xbar, torch.float64, "xbar")
+    mesh.check_local(k, torch.float64, "k")
+    if not (need_kbar or need_bbar):
+        raise ValueError("nothing to compute: need_kbar and need_bbar are both False")
+    kbar = torch.empty_like(xbar) if need_kbar else None
+    bbar = torch.empty_like(xbar) if need_bbar else None
+    opts, hist = _solve_opts(mesh, mode, precond, precond_prec, cheb_order, lmax, rtol, max_iter,
+                             False, inner_rtol, max_outer, check_every, False, False)
+    st = L.SolveStats()
+    status = mesh._lib.sem_solve_backward(mesh.handle, _ptr(x), _ptr(xbar), _ptr(k), float(h2),
+                                          ctypes.byref(opts), _ptr(kbar), _ptr(bbar),
+                                          ctypes.byref(st), _stream())
+    _check(status, "sem_solve_backward")
+    return kbar, bbar, _stats_dict(st, status, hist)
 
 
 def ax_backward(mesh: Mesh, u, wbar, k=None, h2: float = 0.0, need_ubar: bool = True,

@@ -1,11 +1,10 @@
 """Differentiable solve: x = A(k)^{-1} b as a torch.autograd.Function.
 
-Forward: one sem_pcg_solve.  Backward for a cotangent xbar of the
-copy-consistent solution x_L:
-  adjoint right-hand side  Q^T xbar   (sum over the copies of each node),
-  adjoint solve            A(k) lam = Q^T xbar       (A is symmetric: same solve),
-  kbar_q = -sum_ab (D_a lam_L)_q G_ab,q (D_b x_L)_q   (sem_ax_backward),
-  bbar   = lam_L / multiplicity  (the solve reads b as the mean of its copies).
+Forward: one sem_pcg_solve.  Backward: one sem_solve_backward, which runs the
+adjoint solve A(k) lam = R Q^T xbar and forms both gradients in libsem:
+  dL/dk = -sum_ab (D_a lam_L) G_ab (D_b x_L)   (the k-derivative of the operator),
+  dL/db = lam_L / multiplicity                  (b is read as the mean of its copies).
+This module only marshals tensors.
 """
 
 from __future__ import annotations
@@ -31,16 +30,14 @@ class SemSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, xbar):
         k, x = ctx.saved_tensors
-        k = k if ctx.has_k else None
-        mesh = ctx.mesh
+        need_k = ctx.has_k and ctx.needs_input_grad[0]
+        need_b = ctx.needs_input_grad[1]
+        if not (need_k or need_b):
+            return None, None, None, None, None, None
         with torch.no_grad():
-            rhs = api.gs(mesh, xbar.detach().contiguous().clone())
-            lam, _ = api.solve(mesh, rhs, k=k, h2=ctx.h2, rtol=ctx.rtol, max_iter=ctx.max_iter)
-            kbar = None
-            if ctx.has_k and ctx.needs_input_grad[0]:
-                _, kb = api.ax_backward(mesh, x, lam, need_ubar=False, need_kbar=True)
-                kbar = -kb
-            bbar = lam / mesh.multiplicity() if ctx.needs_input_grad[1] else None
+            kbar, bbar, _ = api.solve_backward(
+                ctx.mesh, x, xbar.detach().contiguous(), k=k if ctx.has_k else None, h2=ctx.h2,
+                need_kbar=need_k, need_bbar=need_b, rtol=ctx.rtol, max_iter=ctx.max_iter)
         return kbar, bbar, None, None, None, None
 
 

@@ -1,7 +1,9 @@
 // The C entry points of libsem (declared and documented in include/sem.h).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -340,6 +342,275 @@ static sem_status check_mesh(const sem_mesh* m) {
   return SEM_OK;
 }
 
+// The options of a solve, validated (defaults when opts_in is NULL).
+static sem_status solve_options(const sem_mesh* m, const sem_solve_opts* opts_in,
+                                sem_solve_opts& opts) {
+  if (opts_in) opts = *opts_in;
+  else sem_solve_opts_default(&opts);
+  if (opts.mode != SEM_SOLVE_CG && opts.mode != SEM_SOLVE_MIXED_IR)
+    return fail(SEM_EINVAL, "unknown solve mode");
+  if (opts.precond != SEM_PRECOND_JACOBI && opts.precond != SEM_PRECOND_CHEBYSHEV &&
+      opts.precond != SEM_PRECOND_PMG && opts.precond != SEM_PRECOND_CHEBYSHEV_FIRST)
+    return fail(SEM_EINVAL, "unknown preconditioner");
+  const bool pmg = opts.precond == SEM_PRECOND_PMG;
+  if (pmg && !m->pmg) return fail(SEM_EINVAL, "multigrid preconditioner: call sem_setup_pmg first");
+  if (pmg && opts.precond_prec != SEM_FP32 &&
+      !(opts.precond_prec == SEM_FP64 && opts.mode == SEM_SOLVE_CG))
+    return fail(SEM_EINVAL, "the multigrid cycle runs in SEM_FP32 (or SEM_FP64 in mode CG)");
+  if (opts.cheb_order < 1) return fail(SEM_EINVAL, "cheb_order must be >= 1");
+  if (opts.max_iter < 0) return fail(SEM_EINVAL, "max_iter must be >= 0");
+  if (!(opts.rtol >= 0.0)) return fail(SEM_EINVAL, "rtol must be >= 0");
+  if (opts.mode == SEM_SOLVE_MIXED_IR && opts.fixed_iters)
+    return fail(SEM_EINVAL, "fixed_iters is only available in mode CG");
+  if (opts.mode == SEM_SOLVE_MIXED_IR && !(opts.inner_rtol > 0.0 && opts.inner_rtol < 1.0))
+    return fail(SEM_EINVAL, "inner_rtol must be in (0, 1)");
+  const bool cheb_any =
+      opts.precond == SEM_PRECOND_CHEBYSHEV || opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST;
+  if (cheb_any && !prec_ok((sem_prec)opts.precond_prec))
+    return fail(SEM_EINVAL, "unknown Chebyshev precision");
+  if (opts.mode == SEM_SOLVE_MIXED_IR && cheb_any && opts.precond_prec == SEM_FP64)
+    return fail(SEM_EINVAL, "the inner solve of MIXED_IR runs in FP32 data");
+
+  return SEM_OK;
+}
+
+// How a solve takes its right-hand side and start on the free nodes
+// (`load`: fills bf and xf, tells whether x0 = 0) and what it does with the
+// solution there (`store`).  Both enqueue on the solve's stream.
+using SolveLoad = std::function<sem_status(double* bf, double* xf, bool* x_zero)>;
+using SolveStore = std::function<sem_status(const double* xf)>;
+
+// Everything of a solve between the free-node right-hand side and the
+// free-node solution: preconditioner set-up, the CG or the refinement loop,
+// the null-space projection, the timing and the statistics.
+static sem_status solve_free(const sem_mesh* m, const double* k, double h2,
+                             const sem_solve_opts& opts, const SolveLoad& load,
+                             const SolveStore& store, sem_solve_stats* stats, hipStream_t s) {
+  SolveWork& W = work_of(m);
+  const bool pmg = opts.precond == SEM_PRECOND_PMG;
+  sem_status st = W.init(m, std::max(opts.max_iter, 1));
+  if (st) return st;
+  W.ev_used = 0;
+  hipEvent_t t0, t1;
+  SEM_HIP(hipEventCreate(&t0));
+  SEM_HIP(hipEventCreate(&t1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{t0, t1};
+
+  const bool neumann = m->nullspace && h2 == 0.0;
+  const bool cheb =
+      opts.precond == SEM_PRECOND_CHEBYSHEV || opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST;
+  const int kind = opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST ? 1 : 4;
+  const bool pmg64 = pmg && opts.precond_prec == SEM_FP64;
+  if (pmg && (st = pmg_prepare(m, k, h2, pmg64, s))) return st;
+  double lmax = pmg ? m->pmg->lv[0].rho_hat : opts.lmax;
+  if (cheb && !(lmax > 0.0)) {
+    double est = 0.0;
+    if ((st = estimate_lmax(m, W, k, h2, 20, &est, s))) return st;
+    lmax = 1.1 * est;
+  }
+  SEM_HIP(hipEventRecord(t0, s));
+  if ((st = prepare_dinv(m, W, k, h2, s))) return st;
+  const int64_t nf = m->n_free;
+  double* bf = W.vec<double>(W.bf, nf);
+  double* xf = W.vec<double>(W.x, nf);
+  if (!bf || !xf) return fail(SEM_ENOMEM, "work space");
+  bool x_zero = false;
+  if ((st = load(bf, xf, &x_zero))) return st;
+  if (neumann && (st = free_remove_mean_f64(m, W, bf, s))) return st;
+
+  const Op<double> op64 = op64_of(m, k, h2);
+  Op<float> op32;
+  if ((st = op32_of(m, W, k, h2, s, op32))) return st;
+  Op<float> opc = op32;  // the Chebyshev preconditioner's FP32-data operator
+  opc.lp = lp_of((sem_prec)opts.precond_prec);
+  const double* dinv = W.dinv.as<double>();
+  const float* dinv32 = W.dinv32.as<float>();
+
+  int iters = 0, outer = 0, applies = 0;
+  bool converged = false;
+  int fail_status = 0;
+  double rel = 0.0;
+
+  if (opts.mode == SEM_SOLVE_CG) {
+    CgArgs<double, double> a;
+    a.op = op64;
+    a.b = bf;
+    a.x = xf;
+    a.r = W.vec<double>(W.r, nf);
+    a.p = W.vec<double>(W.p, nf);
+    a.w = W.vec<double>(W.w, nf);
+    a.z = W.vec<double>(W.z, nf);
+    a.wL = W.vec<double>(W.wL, m->nL);
+    if (!a.r || !a.p || !a.w || !a.z || !a.wL) return fail(SEM_ENOMEM, "work space");
+    a.dinv = dinv;
+    a.precond = opts.precond;
+    a.cheb_order = opts.cheb_order;
+    if (pmg) {
+      if (pmg64)
+        a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
+                    const ChebCg& cg, hipStream_t ss, int* ap) {
+          return pmg_precond<double, double>(mm, WW, r, z, cg, ss, ap);
+        };
+      else
+        a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
+                    const ChebCg& cg, hipStream_t ss, int* ap) {
+          return pmg_precond<double, float>(mm, WW, r, z, cg, ss, ap);
+        };
+    } else if (cheb) {
+      const int order = opts.cheb_order;
+      if (opts.precond_prec == SEM_FP64) {
+        a.cheb = [op64, dinv, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const double* r,
+                                           double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
+          return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, cg, ss, ap,
+                                                kind);
+        };
+      } else {
+        a.cheb = [opc, dinv32, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const double* r,
+                                            double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
+          return cheb_apply_dev<double, float>(mm, WW, opc, dinv32, r, z, order, lmax, cg, ss, ap,
+                                               kind);
+        };
+      }
+    }
+    a.rtol = opts.rtol;
+    a.max_it = opts.max_iter;
+    a.fixed = opts.fixed_iters != 0;
+    a.x_zero = x_zero;
+    a.neumann = neumann;
+    a.profile = opts.profile != 0;
+    a.check_every = opts.check_every;
+    if (pmg) a.max_chunk = kPmgMaxChunk;
+    a.hist = opts.residual_history;
+    CgResult res;
+    if ((st = cg_solve<double, double>(m, W, a, res, s))) return st;
+    iters = res.iters;
+    applies = res.applies;
+    converged = res.converged;
+    fail_status = res.status;
+    rel = res.bnorm > 0.0 ? res.rnorm / res.bnorm : 0.0;
+  } else {
+    // FP64 iterative refinement around an FP32 inner CG
+    double* r = W.vec<double>(W.r, nf);
+    float* b32 = W.vec<float>(W.r32, nf);
+    CgArgs<float, float> a;
+    a.op = op32;
+    a.b = b32;
+    a.x = W.vec<float>(W.x32, nf);
+    a.r = W.vec<float>(W.ri32, nf);
+    a.p = W.vec<float>(W.p32, nf);
+    a.w = W.vec<float>(W.w32, nf);
+    a.z = W.vec<float>(W.z32, nf);
+    a.wL = W.vec<float>(W.wL32, m->nL);
+    if (!r || !b32 || !a.x || !a.r || !a.p || !a.w || !a.z || !a.wL)
+      return fail(SEM_ENOMEM, "work space");
+    a.dinv = dinv32;
+    a.precond = opts.precond;
+    a.cheb_order = opts.cheb_order;
+    if (pmg) {
+      a.cheb = [](const sem_mesh* mm, SolveWork& WW, const float* rr, float* z, const ChebCg& cg,
+                  hipStream_t ss, int* ap) {
+        return pmg_precond<float, float>(mm, WW, rr, z, cg, ss, ap);
+      };
+    } else if (cheb) {
+      const int order = opts.cheb_order;
+      a.cheb = [opc, dinv32, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const float* rr,
+                                          float* z, const ChebCg& cg, hipStream_t ss, int* ap) {
+        return cheb_apply_dev<float, float>(mm, WW, opc, dinv32, rr, z, order, lmax, cg, ss, ap,
+                                            kind);
+      };
+    }
+    a.neumann = neumann;
+    a.x_zero = true;
+    a.fixed = false;
+    a.rtol = opts.inner_rtol;
+    a.check_every = opts.check_every;
+    if (pmg) a.max_chunk = kPmgMaxChunk;
+    double bd[3];
+    if ((st = free_dots_f64(m, W, bf, nullptr, bd, s))) return st;
+    const double bnorm = std::sqrt(bd[0]);
+    double rr_sum[2];
+    if (x_zero) {
+      SEM_HIP((launch_convert<double, double>(bf, r, nf, 1.0, s)));
+      rr_sum[0] = bd[0];
+      rr_sum[1] = bd[2];
+    } else {
+      if ((st = ir_residual(m, W, op64, xf, bf, r, rr_sum, s, opts.profile != 0))) return st;
+      ++applies;
+    }
+    if (bnorm == 0.0) {
+      SEM_HIP(launch_fill<double>(xf, nf, 0.0, s));
+      converged = true;
+    }
+    while (!converged) {
+      const double rnorm = std::sqrt(rr_sum[0]);
+      rel = rnorm / bnorm;
+      if (!std::isfinite(rel)) {
+        fail_status = 3;
+        break;
+      }
+      if (rel <= opts.rtol) {
+        converged = true;
+        break;
+      }
+      if (outer >= opts.max_outer || iters >= opts.max_iter) break;
+      const double shift = neumann ? rr_sum[1] / (double)nf : 0.0;
+      if ((st = ir_prepare(m, r, b32, shift, 1.0 / rnorm, s))) return st;
+      a.max_it = std::max(1, opts.max_iter - iters);
+      // inner reduction: inner_rtol, or only what is still missing to reach rtol
+      // (with a 0.3 safety factor), so the last refinement step is short
+      a.rtol = std::min(0.5, std::max(opts.inner_rtol, 0.3 * opts.rtol / rel));
+      CgResult res;
+      if ((st = cg_solve<float, float>(m, W, a, res, s))) return st;
+      iters += res.iters;
+      applies += res.applies;
+      if (res.status == 2 || res.status == 3) {
+        fail_status = res.status;
+        break;
+      }
+      if ((st = ir_update(m, xf, a.x, rnorm, s))) return st;
+      if ((st = ir_residual(m, W, op64, xf, bf, r, rr_sum, s, opts.profile != 0))) return st;
+      ++applies;
+      ++outer;
+    }
+  }
+  if (neumann && (st = free_remove_mean_f64(m, W, xf, s))) return st;
+  if ((st = store(xf))) return st;
+  SEM_HIP(hipEventRecord(t1, s));
+  SEM_HIP(hipEventSynchronize(t1));
+  float ms = 0.f;
+  SEM_HIP(hipEventElapsedTime(&ms, t0, t1));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = iters;
+    stats->outer_iters = outer;
+    stats->operator_applies = applies;
+    stats->converged = converged ? 1 : 0;
+    stats->rel_res = rel;
+    stats->time_ms = ms;
+    stats->lmax = (cheb || pmg) ? lmax : 0.0;
+    double ax_ms = 0.0;
+    for (int i = 0; i + 1 < W.ev_used; i += 2) {
+      float d = 0.f;
+      if (hipEventElapsedTime(&d, W.ev[i], W.ev[i + 1]) == hipSuccess) ax_ms += d;
+    }
+    stats->ax_ms = ax_ms;
+    stats->ax_launches = W.ev_used / 2;
+  }
+  if (fail_status == 2 || fail_status == 3)
+    return fail(SEM_EBREAKDOWN, fail_status == 2 ? "CG breakdown: p.Ap <= 0"
+                                                 : "CG produced a non-finite value");
+  if (!converged && !opts.fixed_iters)
+    return fail(SEM_ENOCONV, "iteration limit reached before the tolerance");
+  return SEM_OK;
+}
+
+
 }  // namespace sem
 
 sem_mesh::~sem_mesh() {
@@ -471,6 +742,11 @@ sem_status sem_setup_mesh(const sem_mesh_desc* desc, void* stream, sem_mesh** ou
   }
   m->n_single = hn.n_single;
   m->split_ok = surf;
+  if (const char* ev = std::getenv("SEM_AX_NT_BYTES")) {
+    char* end = nullptr;
+    const long long v = std::strtoll(ev, &end, 10);
+    if (end != ev && *end == '\0' && v >= 0) m->ax_nt_bytes = (int64_t)v;
+  }
   if ((st = upload(m->lmap2, lmap2, s)) || (st = upload(m->fperm2, fperm2, s))) return st;
   if ((st = upload(m->lmap, hn.lmap, s)) || (st = upload(m->fseg, hn.fseg, s)) ||
       (st = upload(m->fperm, hn.fperm, s)) || (st = upload(m->gseg, hn.gseg, s)) ||
@@ -899,258 +1175,62 @@ sem_status sem_pcg_solve(const sem_mesh* m, const double* b, double* x, const do
   if (!b || !x) return fail(SEM_EINVAL, "b and x must not be NULL");
   if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
   sem_solve_opts opts;
-  if (opts_in) opts = *opts_in;
-  else sem_solve_opts_default(&opts);
-  if (opts.mode != SEM_SOLVE_CG && opts.mode != SEM_SOLVE_MIXED_IR)
-    return fail(SEM_EINVAL, "unknown solve mode");
-  if (opts.precond != SEM_PRECOND_JACOBI && opts.precond != SEM_PRECOND_CHEBYSHEV &&
-      opts.precond != SEM_PRECOND_PMG && opts.precond != SEM_PRECOND_CHEBYSHEV_FIRST)
-    return fail(SEM_EINVAL, "unknown preconditioner");
-  const bool pmg = opts.precond == SEM_PRECOND_PMG;
-  if (pmg && !m->pmg) return fail(SEM_EINVAL, "multigrid preconditioner: call sem_setup_pmg first");
-  if (pmg && opts.precond_prec != SEM_FP32 &&
-      !(opts.precond_prec == SEM_FP64 && opts.mode == SEM_SOLVE_CG))
-    return fail(SEM_EINVAL, "the multigrid cycle runs in SEM_FP32 (or SEM_FP64 in mode CG)");
-  if (opts.cheb_order < 1) return fail(SEM_EINVAL, "cheb_order must be >= 1");
-  if (opts.max_iter < 0) return fail(SEM_EINVAL, "max_iter must be >= 0");
-  if (!(opts.rtol >= 0.0)) return fail(SEM_EINVAL, "rtol must be >= 0");
-  if (opts.mode == SEM_SOLVE_MIXED_IR && opts.fixed_iters)
-    return fail(SEM_EINVAL, "fixed_iters is only available in mode CG");
-  if (opts.mode == SEM_SOLVE_MIXED_IR && !(opts.inner_rtol > 0.0 && opts.inner_rtol < 1.0))
-    return fail(SEM_EINVAL, "inner_rtol must be in (0, 1)");
-  const bool cheb_any =
-      opts.precond == SEM_PRECOND_CHEBYSHEV || opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST;
-  if (cheb_any && !prec_ok((sem_prec)opts.precond_prec))
-    return fail(SEM_EINVAL, "unknown Chebyshev precision");
-  if (opts.mode == SEM_SOLVE_MIXED_IR && cheb_any && opts.precond_prec == SEM_FP64)
-    return fail(SEM_EINVAL, "the inner solve of MIXED_IR runs in FP32 data");
-
+  if (sem_status st = solve_options(m, opts_in, opts)) return st;
   hipStream_t s = (hipStream_t)stream;
-  SolveWork& W = work_of(m);
-  sem_status st = W.init(m, std::max(opts.max_iter, 1));
-  if (st) return st;
-  W.ev_used = 0;
-  hipEvent_t t0, t1;
-  SEM_HIP(hipEventCreate(&t0));
-  SEM_HIP(hipEventCreate(&t1));
-  struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-    }
-  } guard{t0, t1};
+  // b and x0 are read as the mean of their copies
+  const SolveLoad load = [&](double* bf, double* xf, bool* x_zero) -> sem_status {
+    SEM_HIP((launch_local_to_free_avg<double, double>(m, b, bf, s)));
+    SEM_HIP((launch_local_to_free_avg<double, double>(m, x, xf, s)));
+    double xd[3];
+    if (sem_status st = free_dots_f64(m, work_of(m), xf, nullptr, xd, s)) return st;
+    if (!std::isfinite(xd[0])) return fail(SEM_EINVAL, "x0 is not finite");
+    *x_zero = xd[0] == 0.0;
+    return SEM_OK;
+  };
+  const SolveStore store = [&](const double* xf) -> sem_status {
+    SEM_HIP((launch_free_to_local<double, double>(m, xf, x, s)));
+    return SEM_OK;
+  };
+  return solve_free(m, k, h2, opts, load, store, stats, s);
+}
 
-  const bool neumann = m->nullspace && h2 == 0.0;
-  const bool cheb =
-      opts.precond == SEM_PRECOND_CHEBYSHEV || opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST;
-  const int kind = opts.precond == SEM_PRECOND_CHEBYSHEV_FIRST ? 1 : 4;
-  const bool pmg64 = pmg && opts.precond_prec == SEM_FP64;
-  if (pmg && (st = pmg_prepare(m, k, h2, pmg64, s))) return st;
-  double lmax = pmg ? m->pmg->lv[0].rho_hat : opts.lmax;
-  if (cheb && !(lmax > 0.0)) {
-    double est = 0.0;
-    if ((st = estimate_lmax(m, W, k, h2, 20, &est, s))) return st;
-    lmax = 1.1 * est;
-  }
-  SEM_HIP(hipEventRecord(t0, s));
-  if ((st = prepare_dinv(m, W, k, h2, s))) return st;
-  const int64_t nf = m->n_free;
-  double* bf = W.vec<double>(W.bf, nf);
-  double* xf = W.vec<double>(W.x, nf);
-  if (!bf || !xf) return fail(SEM_ENOMEM, "work space");
-  SEM_HIP((launch_local_to_free_avg<double, double>(m, b, bf, s)));
-  SEM_HIP((launch_local_to_free_avg<double, double>(m, x, xf, s)));
-  if (neumann && (st = free_remove_mean_f64(m, W, bf, s))) return st;
-  double xd[3];
-  if ((st = free_dots_f64(m, W, xf, nullptr, xd, s))) return st;
-  const bool x_zero = (xd[0] == 0.0);
-  if (!std::isfinite(xd[0])) return fail(SEM_EINVAL, "x0 is not finite");
-
-  const Op<double> op64 = op64_of(m, k, h2);
-  Op<float> op32;
-  if ((st = op32_of(m, W, k, h2, s, op32))) return st;
-  Op<float> opc = op32;  // the Chebyshev preconditioner's FP32-data operator
-  opc.lp = lp_of((sem_prec)opts.precond_prec);
-  const double* dinv = W.dinv.as<double>();
-  const float* dinv32 = W.dinv32.as<float>();
-
-  int iters = 0, outer = 0, applies = 0;
-  bool converged = false;
-  int fail_status = 0;
-  double rel = 0.0;
-
-  if (opts.mode == SEM_SOLVE_CG) {
-    CgArgs<double, double> a;
-    a.op = op64;
-    a.b = bf;
-    a.x = xf;
-    a.r = W.vec<double>(W.r, nf);
-    a.p = W.vec<double>(W.p, nf);
-    a.w = W.vec<double>(W.w, nf);
-    a.z = W.vec<double>(W.z, nf);
-    a.wL = W.vec<double>(W.wL, m->nL);
-    if (!a.r || !a.p || !a.w || !a.z || !a.wL) return fail(SEM_ENOMEM, "work space");
-    a.dinv = dinv;
-    a.precond = opts.precond;
-    a.cheb_order = opts.cheb_order;
-    if (pmg) {
-      if (pmg64)
-        a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
-                    const ChebCg& cg, hipStream_t ss, int* ap) {
-          return pmg_precond<double, double>(mm, WW, r, z, cg, ss, ap);
-        };
-      else
-        a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
-                    const ChebCg& cg, hipStream_t ss, int* ap) {
-          return pmg_precond<double, float>(mm, WW, r, z, cg, ss, ap);
-        };
-    } else if (cheb) {
-      const int order = opts.cheb_order;
-      if (opts.precond_prec == SEM_FP64) {
-        a.cheb = [op64, dinv, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                           double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, cg, ss, ap,
-                                                kind);
-        };
-      } else {
-        a.cheb = [opc, dinv32, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                            double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, float>(mm, WW, opc, dinv32, r, z, order, lmax, cg, ss, ap,
-                                               kind);
-        };
-      }
+sem_status sem_solve_backward(const sem_mesh* m, const double* x, const double* xbar,
+                              const double* k, double h2, const sem_solve_opts* opts_in,
+                              double* kbar, double* bbar, sem_solve_stats* stats, void* stream) {
+  if (sem_status st = check_mesh(m)) return st;
+  if (!xbar) return fail(SEM_EINVAL, "xbar must not be NULL");
+  if (!kbar && !bbar) return fail(SEM_EINVAL, "kbar and bbar are both NULL");
+  if (kbar && !x) return fail(SEM_EINVAL, "kbar needs the forward solution x");
+  if (kbar && (kbar == x || kbar == bbar))
+    return fail(SEM_EINVAL, "kbar must not alias x or bbar");
+  if (bbar && bbar == x) return fail(SEM_EINVAL, "bbar must not alias x");
+  if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  sem_solve_opts opts;
+  if (sem_status st = solve_options(m, opts_in, opts)) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // adjoint right-hand side R Q^T xbar (the transpose of copying the free
+  // solution to every local copy), adjoint solve from zero
+  const SolveLoad load = [&](double* bf, double* xf, bool* x_zero) -> sem_status {
+    SEM_HIP((launch_free_sum<double, double>(m, xbar, bf, s)));
+    SEM_HIP(launch_fill<double>(xf, m->n_free, 0.0, s));
+    *x_zero = true;
+    return SEM_OK;
+  };
+  // lambda = the adjoint solution: dL/dk = -kbar(lambda_L, x_L); dL/db at a
+  // copy = lambda / (copies of its node), the transpose of reading b as the
+  // mean of its copies
+  const SolveStore store = [&](const double* lam) -> sem_status {
+    if (kbar) {
+      SolveWork& W = work_of(m);
+      double* lamL = W.vec<double>(W.wL, m->nL);
+      if (!lamL) return fail(SEM_ENOMEM, "work space");
+      SEM_HIP((launch_free_to_local<double, double>(m, lam, lamL, s)));
+      SEM_HIP(launch_ax_kbar(m, x, lamL, kbar, -1.0, s));
     }
-    a.rtol = opts.rtol;
-    a.max_it = opts.max_iter;
-    a.fixed = opts.fixed_iters != 0;
-    a.x_zero = x_zero;
-    a.neumann = neumann;
-    a.profile = opts.profile != 0;
-    a.check_every = opts.check_every;
-    if (pmg) a.max_chunk = kPmgMaxChunk;
-    a.hist = opts.residual_history;
-    CgResult res;
-    if ((st = cg_solve<double, double>(m, W, a, res, s))) return st;
-    iters = res.iters;
-    applies = res.applies;
-    converged = res.converged;
-    fail_status = res.status;
-    rel = res.bnorm > 0.0 ? res.rnorm / res.bnorm : 0.0;
-  } else {
-    // FP64 iterative refinement around an FP32 inner CG
-    double* r = W.vec<double>(W.r, nf);
-    float* b32 = W.vec<float>(W.r32, nf);
-    CgArgs<float, float> a;
-    a.op = op32;
-    a.b = b32;
-    a.x = W.vec<float>(W.x32, nf);
-    a.r = W.vec<float>(W.ri32, nf);
-    a.p = W.vec<float>(W.p32, nf);
-    a.w = W.vec<float>(W.w32, nf);
-    a.z = W.vec<float>(W.z32, nf);
-    a.wL = W.vec<float>(W.wL32, m->nL);
-    if (!r || !b32 || !a.x || !a.r || !a.p || !a.w || !a.z || !a.wL)
-      return fail(SEM_ENOMEM, "work space");
-    a.dinv = dinv32;
-    a.precond = opts.precond;
-    a.cheb_order = opts.cheb_order;
-    if (pmg) {
-      a.cheb = [](const sem_mesh* mm, SolveWork& WW, const float* rr, float* z, const ChebCg& cg,
-                  hipStream_t ss, int* ap) {
-        return pmg_precond<float, float>(mm, WW, rr, z, cg, ss, ap);
-      };
-    } else if (cheb) {
-      const int order = opts.cheb_order;
-      a.cheb = [opc, dinv32, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const float* rr,
-                                          float* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-        return cheb_apply_dev<float, float>(mm, WW, opc, dinv32, rr, z, order, lmax, cg, ss, ap,
-                                            kind);
-      };
-    }
-    a.neumann = neumann;
-    a.x_zero = true;
-    a.fixed = false;
-    a.rtol = opts.inner_rtol;
-    a.check_every = opts.check_every;
-    if (pmg) a.max_chunk = kPmgMaxChunk;
-    double bd[3];
-    if ((st = free_dots_f64(m, W, bf, nullptr, bd, s))) return st;
-    const double bnorm = std::sqrt(bd[0]);
-    double rr_sum[2];
-    if (x_zero) {
-      SEM_HIP((launch_convert<double, double>(bf, r, nf, 1.0, s)));
-      rr_sum[0] = bd[0];
-      rr_sum[1] = bd[2];
-    } else {
-      if ((st = ir_residual(m, W, op64, xf, bf, r, rr_sum, s, opts.profile != 0))) return st;
-      ++applies;
-    }
-    if (bnorm == 0.0) {
-      SEM_HIP(launch_fill<double>(xf, nf, 0.0, s));
-      converged = true;
-    }
-    while (!converged) {
-      const double rnorm = std::sqrt(rr_sum[0]);
-      rel = rnorm / bnorm;
-      if (!std::isfinite(rel)) {
-        fail_status = 3;
-        break;
-      }
-      if (rel <= opts.rtol) {
-        converged = true;
-        break;
-      }
-      if (outer >= opts.max_outer || iters >= opts.max_iter) break;
-      const double shift = neumann ? rr_sum[1] / (double)nf : 0.0;
-      if ((st = ir_prepare(m, r, b32, shift, 1.0 / rnorm, s))) return st;
-      a.max_it = std::max(1, opts.max_iter - iters);
-      // inner reduction: inner_rtol, or only what is still missing to reach rtol
-      // (with a 0.3 safety factor), so the last refinement step is short
-      a.rtol = std::min(0.5, std::max(opts.inner_rtol, 0.3 * opts.rtol / rel));
-      CgResult res;
-      if ((st = cg_solve<float, float>(m, W, a, res, s))) return st;
-      iters += res.iters;
-      applies += res.applies;
-      if (res.status == 2 || res.status == 3) {
-        fail_status = res.status;
-        break;
-      }
-      if ((st = ir_update(m, xf, a.x, rnorm, s))) return st;
-      if ((st = ir_residual(m, W, op64, xf, bf, r, rr_sum, s, opts.profile != 0))) return st;
-      ++applies;
-      ++outer;
-    }
-  }
-  if (neumann && (st = free_remove_mean_f64(m, W, xf, s))) return st;
-  SEM_HIP((launch_free_to_local<double, double>(m, xf, x, s)));
-  SEM_HIP(hipEventRecord(t1, s));
-  SEM_HIP(hipEventSynchronize(t1));
-  float ms = 0.f;
-  SEM_HIP(hipEventElapsedTime(&ms, t0, t1));
-  if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    stats->iters = iters;
-    stats->outer_iters = outer;
-    stats->operator_applies = applies;
-    stats->converged = converged ? 1 : 0;
-    stats->rel_res = rel;
-    stats->time_ms = ms;
-    stats->lmax = (cheb || pmg) ? lmax : 0.0;
-    double ax_ms = 0.0;
-    for (int i = 0; i + 1 < W.ev_used; i += 2) {
-      float d = 0.f;
-      if (hipEventElapsedTime(&d, W.ev[i], W.ev[i + 1]) == hipSuccess) ax_ms += d;
-    }
-    stats->ax_ms = ax_ms;
-    stats->ax_launches = W.ev_used / 2;
-  }
-  if (fail_status == 2 || fail_status == 3)
-    return fail(SEM_EBREAKDOWN, fail_status == 2 ? "CG breakdown: p.Ap <= 0"
-                                                 : "CG produced a non-finite value");
-  if (!converged && !opts.fixed_iters)
-    return fail(SEM_ENOCONV, "iteration limit reached before the tolerance");
-  return SEM_OK;
+    if (bbar) SEM_HIP(launch_free_to_local_per_copy(m, lam, bbar, s));
+    return SEM_OK;
+  };
+  return solve_free(m, k, h2, opts, load, store, stats, s);
 }
 
 sem_status sem_ax_backward(const sem_mesh* m, const double* u, const double* wbar, const double* k,
@@ -1166,7 +1246,7 @@ sem_status sem_ax_backward(const sem_mesh* m, const double* u, const double* wba
     if (e != hipSuccess) return hip_fail(e, "sem_ax_backward (ubar)");
   }
   if (kbar) {
-    hipError_t e = launch_ax_kbar(m, u, wbar, kbar, s);
+    hipError_t e = launch_ax_kbar(m, u, wbar, kbar, 1.0, s);
     if (e != hipSuccess) return hip_fail(e, "sem_ax_backward (kbar)");
   }
   return SEM_OK;

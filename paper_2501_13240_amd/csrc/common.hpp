@@ -222,8 +222,12 @@ struct sem_mesh {
   sem::DevBuf fperm2;                   // fperm with shared copies at their surface slots
   int64_t n_single = 0;                 // free nodes [0, n_single) have one local copy
   bool split_ok = false;                // every shared copy lies on its element's surface
+  // the in-solve operator stores shared copies nontemporally when the local
+  // array is larger than this (plain stores keep them in the memory-side
+  // cache for the segmented sum that follows): 128 MB, or SEM_AX_NT_BYTES
+  // read at sem_setup_mesh
+  int64_t ax_nt_bytes = int64_t(128) << 20;
   sem::DevBuf gseg, gperm, dlist;       // local gather-scatter tables, Dirichlet copies
-  sem::DevBuf fcount;                   // copies per free node as double (for averaging)
   // cached Jacobi inverse and Chebyshev bound for k == NULL
   double cached_h2 = -1.0;
   bool dinv_valid = false;
@@ -263,8 +267,9 @@ hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* 
                            const int32_t* skip);
 bool ax_split_available(const sem_mesh* m);
 int ax_split_parts(int N);
+// kbar = sign sum_ab (D_a wbar) G_ab (D_b u) at every local point
 hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
-                          hipStream_t s);
+                          double sign, hipStream_t s);
 template <typename T>
 hipError_t launch_mass(int64_t n, const T* B, const T* u, T* w, hipStream_t s);
 
@@ -287,6 +292,9 @@ template <typename Tin, typename Tout>
 hipError_t launch_free_to_local(const sem_mesh* m, const Tin* vf, Tout* vL, hipStream_t s);
 template <typename Tin, typename Tout>
 hipError_t launch_free_sum(const sem_mesh* m, const Tin* wL, Tout* wf, hipStream_t s);
+// vL[q] = vf[f] / (copies of f), f = lmap[q] (0 at Dirichlet copies)
+hipError_t launch_free_to_local_per_copy(const sem_mesh* m, const double* vf, double* vL,
+                                         hipStream_t s);
 
 // generic small kernels
 template <typename T>

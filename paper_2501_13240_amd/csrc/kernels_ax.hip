@@ -590,12 +590,14 @@ bool prefer_mfma(int N, bool gather, bool fp32) {
   return N >= 5;
 }
 
-// kbar_q = sum_ab (D_a wbar)_q G_ab,q (D_b u)_q: the derivative of the
-// operator in k contracted with a cotangent (same mapping, 72 B per point).
+// kbar_q = sign sum_ab (D_a wbar)_q G_ab,q (D_b u)_q: the derivative of the
+// operator in k contracted with a cotangent (same mapping, 72 B per point);
+// sign = -1 gives the gradient of a solve (exact negation).
 template <int N>
 __global__ __launch_bounds__(Shape<N>::BT) void kbar_kernel(
     const double* __restrict__ u, const double* __restrict__ wb, double* __restrict__ kbar,
-    const double* __restrict__ G, const double* __restrict__ D, const int64_t E) {
+    const double* __restrict__ G, const double* __restrict__ D, const int64_t E,
+    const double sign) {
   using S = Shape<N>;
   constexpr int n1 = S::n1, P2 = S::P2, P = S::P, EPB = S::EPB, PPT = S::PPT, TPE = S::TPE;
   __shared__ double su[EPB][P];
@@ -645,7 +647,7 @@ __global__ __launch_bounds__(Shape<N>::BT) void kbar_kernel(
       const double vr = gc[0] * ur + gc[1] * us + gc[2] * ut;
       const double vs = gc[1] * ur + gc[3] * us + gc[4] * ut;
       const double vt = gc[2] * ur + gc[4] * us + gc[5] * ut;
-      st_stream(wr * vr + ws * vs + wt * vt, kbar + e * P + q);
+      st_stream(sign * (wr * vr + ws * vs + wt * vt), kbar + e * P + q);
     }
   }
 }
@@ -698,11 +700,11 @@ hipError_t run_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, cons
 
 template <int N>
 hipError_t run_kbar(const sem_mesh* m, const double* u, const double* wb, double* kbar,
-                    hipStream_t s) {
+                    double sign, hipStream_t s) {
   using S = Shape<N>;
   const int64_t grid = (m->E + S::EPB - 1) / S::EPB;
   hipLaunchKernelGGL((kbar_kernel<N>), dim3((unsigned)grid), dim3(S::BT), 0, s, u, wb, kbar,
-                     m->G64.as<double>(), m->D64.as<double>(), m->E);
+                     m->G64.as<double>(), m->D64.as<double>(), m->E, sign);
   return hipGetLastError();
 }
 
@@ -742,11 +744,11 @@ hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epa
     using M = MShape<N>;
     // shared-copy results stay in the memory-side cache for the segmented
     // sum when the local array fits well inside it (256 MB): plain stores up
-    // to 128 MB (the 32x32x16, N = 7 box: 67 MB, 1.1 % faster per
-    // iteration), nontemporal above (the 32^3, N = 9 cube: 262 MB, 2.2 %)
-    // (MODE 2 plain, MODE 3 nontemporal: a run-time switch in the kernel cost
-    // what the nontemporal stores save)
-    if (m->nL * (int64_t)sizeof(T) <= (int64_t(128) << 20))
+    // to m->ax_nt_bytes, 128 MB by default (the 32x32x16, N = 7 box: 67 MB,
+    // 1.1 % faster per iteration), nontemporal above (the 32^3, N = 9 cube:
+    // 262 MB, 2.2 %) (MODE 2 plain, MODE 3 nontemporal: a run-time switch in
+    // the kernel cost what the nontemporal stores save)
+    if (m->nL * (int64_t)sizeof(T) <= m->ax_nt_bytes)
       hipLaunchKernelGGL((ax_mfma_kernel<N, T, 2, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
                          u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
     else
@@ -806,18 +808,18 @@ template hipError_t launch_ax_split<float>(const sem_mesh*, const float*, float*
                                            const float*, hipStream_t, const int32_t*);
 
 hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
-                          hipStream_t s) {
+                          double sign, hipStream_t s) {
   switch (m->N) {
-    case 1: return run_kbar<1>(m, u, wbar, kbar, s);
-    case 2: return run_kbar<2>(m, u, wbar, kbar, s);
-    case 3: return run_kbar<3>(m, u, wbar, kbar, s);
-    case 4: return run_kbar<4>(m, u, wbar, kbar, s);
-    case 5: return run_kbar<5>(m, u, wbar, kbar, s);
-    case 6: return run_kbar<6>(m, u, wbar, kbar, s);
-    case 7: return run_kbar<7>(m, u, wbar, kbar, s);
-    case 8: return run_kbar<8>(m, u, wbar, kbar, s);
-    case 9: return run_kbar<9>(m, u, wbar, kbar, s);
-    case 10: return run_kbar<10>(m, u, wbar, kbar, s);
+    case 1: return run_kbar<1>(m, u, wbar, kbar, sign, s);
+    case 2: return run_kbar<2>(m, u, wbar, kbar, sign, s);
+    case 3: return run_kbar<3>(m, u, wbar, kbar, sign, s);
+    case 4: return run_kbar<4>(m, u, wbar, kbar, sign, s);
+    case 5: return run_kbar<5>(m, u, wbar, kbar, sign, s);
+    case 6: return run_kbar<6>(m, u, wbar, kbar, sign, s);
+    case 7: return run_kbar<7>(m, u, wbar, kbar, sign, s);
+    case 8: return run_kbar<8>(m, u, wbar, kbar, sign, s);
+    case 9: return run_kbar<9>(m, u, wbar, kbar, sign, s);
+    case 10: return run_kbar<10>(m, u, wbar, kbar, sign, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -68,6 +68,17 @@ __global__ void free_to_local_kernel(int64_t nL, const int32_t* __restrict__ lma
   }
 }
 
+// vL[q] = vf[f] / (number of copies of f), f = lmap[q]; 0 at Dirichlet copies
+__global__ void free_to_local_per_copy_kernel(int64_t nL, const int32_t* __restrict__ lmap,
+                                              const int32_t* __restrict__ seg,
+                                              const double* __restrict__ vf,
+                                              double* __restrict__ vL) {
+  GRID_STRIDE(q, nL) {
+    const int32_t f = lmap[q];
+    vL[q] = f >= 0 ? vf[f] / (double)(seg[f + 1] - seg[f]) : 0.0;
+  }
+}
+
 template <typename T>
 __global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
   GRID_STRIDE(a, n) p[a] = v;
@@ -149,6 +160,13 @@ hipError_t launch_free_to_local(const sem_mesh* m, const Tin* vf, Tout* vL, hipS
 }
 template hipError_t launch_free_to_local<double, double>(const sem_mesh*, const double*, double*,
                                                         hipStream_t);
+
+hipError_t launch_free_to_local_per_copy(const sem_mesh* m, const double* vf, double* vL,
+                                         hipStream_t s) {
+  hipLaunchKernelGGL(free_to_local_per_copy_kernel, dim3(grid_for(m->nL)), dim3(kVecBlock), 0, s,
+                     m->nL, m->lmap.as<int32_t>(), m->fseg.as<int32_t>(), vf, vL);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s) {

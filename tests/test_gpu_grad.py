@@ -98,3 +98,40 @@ def test_ax_backward_dot_product_identities():
     a = float(torch.sum(wb * sem.ax(M, u, k=k, h2=h2)))
     c = float(torch.sum(u * ub))
     assert abs(a - c) <= 1e-12 * abs(a)
+
+
+@pytest.mark.parametrize("case", ["helmholtz_k", "neumann"])
+def test_solve_backward_matches_oracle_adjoint(case):
+    """sem_solve_backward through the C ABI for an arbitrary cotangent xbar
+    (not copy-consistent): the oracle's adjoint solve A lam = R Q^T xbar, then
+    dL/dk = -kbar(lam_L, x_L) and dL/db = lam_L / multiplicity."""
+    if case == "helmholtz_k":
+        m, fld = config_mesh(4, N=5, shape=(4, 4, 3))
+        k_np, h2 = fld["k"], fld["h2"]
+        P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N, k=k_np, h2=h2)
+        b_or = P.rhs_from_source(fld["f"])
+    else:  # all-Neumann, constant mode removed, k = 1
+        m, fld = config_mesh(5, N=7, shape=(3, 3, 3))
+        k_np, h2 = None, 0.0
+        P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+        b_or = P.num.from_local_consistent(fld["b"])
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    kd = None if k_np is None else torch.tensor(k_np, device="cuda")
+    x_or = P.solve(b_or, rtol=1e-14)["x"]
+    xbar = np.random.default_rng(8).standard_normal((m.E, m.P))
+    lam = P.solve(P.num.R(P.num.Qt(xbar)), rtol=1e-14)["x"]
+    kbar_or = -oracle.kgrad_contraction(P.num.to_local(x_or), P.num.to_local(lam), P.G, m.N)
+    mult = P.num.mult[P.num.lid]
+    bbar_or = P.num.to_local(lam) / mult
+    x = torch.tensor(P.num.to_local(x_or), device="cuda")
+    kbar, bbar, st = sem.solve_backward(M, x, torch.tensor(xbar, device="cuda"), k=kd, h2=h2,
+                                        rtol=1e-14, max_iter=20000)
+    e_k = np.linalg.norm(kbar.cpu().numpy() - kbar_or) / np.linalg.norm(kbar_or)
+    e_b = np.linalg.norm(bbar.cpu().numpy() - bbar_or) / np.linalg.norm(bbar_or)
+    print(f"{case}: adjoint solve {st['iters']} it; kbar {e_k:.2e}, bbar {e_b:.2e}")
+    assert st["converged"] == 1
+    assert e_k <= 1e-9 and e_b <= 1e-9
+    # one output at a time gives the same values
+    kb1, none_b, _ = sem.solve_backward(M, x, torch.tensor(xbar, device="cuda"), k=kd, h2=h2,
+                                        need_bbar=False, rtol=1e-14, max_iter=20000)
+    assert none_b is None and torch.equal(kb1, kbar)

@@ -129,10 +129,11 @@ def _true_rel_residual(P, x_local, b_free):
     return np.linalg.norm(b_free - P.apply(xf)) / np.linalg.norm(b_free), xf
 
 
+@pytest.mark.parametrize("N", [7, 9])  # the precision workload at both orders
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
 @pytest.mark.parametrize("mode", ["cg", "mixed_ir"])
-def test_solves_with_16bit_chebyshev_reach_fp64_tolerance(fmt, mode):
-    m, fld = config_mesh(1, N=7)
+def test_solves_with_16bit_chebyshev_reach_fp64_tolerance(fmt, mode, N):
+    m, fld = config_mesh(1, N=N)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
     P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
     f = fld["f"] * 3 * np.pi ** 2
@@ -143,7 +144,7 @@ def test_solves_with_16bit_chebyshev_reach_fp64_tolerance(fmt, mode):
                       rtol=1e-10)
     _, st32 = sem.solve(M, bL, mode=mode, precond="chebyshev", precond_prec="fp32", rtol=1e-10)
     res, xf = _true_rel_residual(P, x.cpu().numpy(), b_or)
-    print(f"{mode} + {fmt} Chebyshev: iters {st['iters']} (fp32 Chebyshev {st32['iters']}), "
+    print(f"N={N} {mode} + {fmt} Chebyshev: iters {st['iters']} (fp32 Chebyshev {st32['iters']}), "
           f"outer {st['outer_iters']}, true rel res {res:.2e}, err vs oracle {rel(xf, ref['x']):.2e}")
     assert st["converged"] == 1
     assert res <= (1.0e-10 if mode == "cg" else 1.2e-10)

@@ -35,6 +35,19 @@ def dev(a, dtype=torch.float64):
     return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
+@pytest.fixture(params=["plain", "nontemporal"])
+def store_form(request, monkeypatch):
+    """Which form of the in-solve operator a mesh set up in the test uses:
+    shared-copy results written with plain stores (the default up to a
+    128 MB local array) or with nontemporal ones (the default above;
+    SEM_AX_NT_BYTES=0, read at mesh set-up, forces them at any size)."""
+    if request.param == "nontemporal":
+        monkeypatch.setenv("SEM_AX_NT_BYTES", "0")
+    else:
+        monkeypatch.delenv("SEM_AX_NT_BYTES", raising=False)
+    return request.param
+
+
 def small_mesh(N, shape=(3, 2, 3), dirichlet="all", deform=True, periodic=(False, False, False)):
     return box_mesh(N, shape, (1.0, 1.5, 1.0), periodic=periodic, dirichlet=dirichlet,
                     jitter=0.05, deform=dict(a=0.15, seed=3, kind="walls") if deform else None)
@@ -177,7 +190,7 @@ def test_pcg_config1_jacobi_matches_oracle():
     assert np.abs(P.num.gs(xl) / P.num.mult[P.num.lid] - xl).max() <= 1e-15 * np.abs(xl).max()
 
 
-def test_pcg_fixed_iterations_periodic_box_histories_agree():
+def test_pcg_fixed_iterations_periodic_box_histories_agree(store_form):
     m, fld = config_mesh(2, shape=(6, 6, 4))
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
     P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
@@ -190,7 +203,7 @@ def test_pcg_fixed_iterations_periodic_box_histories_agree():
 
 
 @pytest.mark.parametrize("N", [4, 7])  # gather-form and split in-solve operator
-def test_pcg_neumann_matches_oracle(N):
+def test_pcg_neumann_matches_oracle(N, store_form):
     m, fld = config_mesh(5, N=N, shape=(4, 4, 4))
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
     P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
@@ -304,32 +317,119 @@ def test_graph_replayed_solve_matches_eager_launches(precond):
     assert torch.equal(xf_e, xf_g)
 
 
-@pytest.mark.parametrize("cfg,shape", [(2, None), (5, (26, 26, 26))])
-def test_pcg_full_size_true_residual(cfg, shape):
-    """The benchmark's solve at full size (32x32x16 elements, N = 7: the split
-    in-solve operator with plain shared-copy stores, 67 MB local arrays) and a
-    26^3-element, N = 9 Neumann cube (141 MB: the nontemporal-store form),
-    with the Jacobi kernels that keep z in place of r, eager launches.  Too
-    large for the oracle, so: the true residual, formed with the stand-alone
-    operator (parity-tested against the oracle above), meets the tolerance; a
-    fixed solve of the same length gives the same x bit for bit; copies of a
-    node agree and Dirichlet copies are exact zeros."""
-    m, fld = config_mesh(cfg, shape=shape)
+def test_store_forms_give_identical_iterates(monkeypatch):
+    """The two stores of the in-solve operator differ only in their cache
+    hint: 40 fixed iterations give the same x bit for bit."""
+    m, fld = config_mesh(2, shape=(6, 6, 4))
+    xs = []
+    for nt in (None, "0"):
+        if nt is None:
+            monkeypatch.delenv("SEM_AX_NT_BYTES", raising=False)
+        else:
+            monkeypatch.setenv("SEM_AX_NT_BYTES", nt)
+        M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+        xs.append(sem.solve(M, dev(fld["b"]), max_iter=40, fixed_iters=True)[0])
+        M.close()
+    assert torch.equal(xs[0], xs[1])
+
+
+@pytest.fixture(scope="module")
+def headline():
+    """The benchmark workload at full size (32x32x16 elements, N = 7,
+    5,669,888 unique nodes) with the oracle's assembled problem on it."""
+    m, fld = config_mesh(2)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    return m, fld, P
+
+
+@pytest.mark.timeout(900)
+def test_pcg_headline_100_iterations_match_oracle(headline, monkeypatch):
+    """The benchmark's step at full size against the oracle's own 100
+    Jacobi-PCG iterations: residual histories and x_100 to 1e-8 relative,
+    for both stores of the in-solve operator (plain: the default at this
+    67 MB size; nontemporal: forced)."""
+    m, fld, P = headline
+    b_or = P.num.from_local_consistent(fld["b"])
+    print("oracle: 100 Jacobi-PCG iterations on the full benchmark mesh ...", flush=True)
+    ref = P.solve(b_or, rtol=1e-30, max_iter=100, fixed_iters=True)
+    for nt in (None, "0"):
+        if nt is None:
+            monkeypatch.delenv("SEM_AX_NT_BYTES", raising=False)
+        else:
+            monkeypatch.setenv("SEM_AX_NT_BYTES", nt)
+        M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+        x, st = sem.solve(M, dev(fld["b"]), max_iter=100, fixed_iters=True, history=True)
+        assert st["iters"] == 100
+        eh = np.max(np.abs(st["history"] / ref["res_hist"] - 1.0))
+        ex = rel(P.num.from_local_consistent(x.cpu().numpy()), ref["x"])
+        print(f"store {'nontemporal' if nt else 'plain'}: history max rel diff {eh:.2e}, "
+              f"x_100 rel diff {ex:.2e}", flush=True)
+        np.testing.assert_allclose(st["history"], ref["res_hist"], rtol=1e-8)
+        assert ex <= 1e-8
+        M.close()
+
+
+@pytest.mark.timeout(900)
+def test_pcg_headline_converged_true_residual_by_oracle(headline):
+    """Jacobi PCG and the p-multigrid-preconditioned solve with the FP32 cycle
+    to 1e-10 on the full benchmark mesh: the oracle's FP64 operator gives the
+    true residual; a fixed solve of the Jacobi iteration count gives the same
+    x bit for bit; copies of a node agree and Dirichlet copies are exact
+    zeros."""
+    m, fld, P = headline
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
     b = dev(fld["b"])
     x, st = sem.solve(M, b, rtol=1e-10)
-    r = sem.mask(M, (b - sem.gs(M, sem.ax(M, x))).contiguous())
-    mult = M.multiplicity()
-    bb = sem.mask(M, b.clone())
-    res = float(torch.sqrt(torch.sum(r * r / mult) / torch.sum(bb * bb / mult)))
-    print(f"config {cfg} Jacobi PCG: {st['iters']} iterations, true res {res:.2e}")
-    assert st["converged"] == 1 and res <= 1.2e-10
     xf, stf = sem.solve(M, b, max_iter=st["iters"], fixed_iters=True)
     assert torch.equal(x, xf)
+    mult = M.multiplicity()
     assert float((sem.gs(M, x.clone()) / mult - x).abs().max()) <= 1e-15 * float(x.abs().max())
-    if m.dirichlet is not None:
-        d = torch.as_tensor(m.dirichlet != 0, device="cuda")
-        assert int(torch.count_nonzero(x[d])) == 0
+    d = torch.as_tensor(m.dirichlet != 0, device="cuda")
+    assert int(torch.count_nonzero(x[d])) == 0
+    M.setup_pmg()
+    xm, stm = sem.solve(M, b, rtol=1e-10, precond="pmg", precond_prec="fp32")
+    b_or = P.num.from_local_consistent(fld["b"])
+    res, x_or = _true_rel_residual(P, x.cpu().numpy(), b_or)
+    res_m, xm_or = _true_rel_residual(P, xm.cpu().numpy(), b_or)
+    print(f"benchmark mesh to 1e-10: Jacobi {st['iters']} it, oracle true res {res:.2e}; "
+          f"pMG FP32 cycle {stm['iters']} it, oracle true res {res_m:.2e}; "
+          f"x difference {rel(xm_or, x_or):.2e}", flush=True)
+    assert st["converged"] == 1 and res <= 1.2e-10
+    assert stm["converged"] == 1 and res_m <= 1.2e-10
+    M.close()
+
+
+@pytest.mark.timeout(1200)
+def test_neumann_cube_full_size_solves_true_residual_by_oracle():
+    """The mixed-versus-FP64 workload at full size (32^3 elements, N = 9,
+    all-Neumann, 24,137,569 unique nodes; 262 MB local arrays, so the solve
+    uses the nontemporal-store operator): FP64 Jacobi CG and FP64 flexible CG
+    with the FP32 p-multigrid cycle to 1e-10; the oracle's FP64 operator gives
+    the true residual of both (<= 1.2e-10), and both have zero mean."""
+    m, fld = config_mesh(5)
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    b = dev(fld["b"])
+    x64, st64 = sem.solve(M, b, rtol=1e-10, max_iter=30000)
+    M.setup_pmg()
+    x32, st32 = sem.solve(M, b, rtol=1e-10, precond="pmg", precond_prec="fp32")
+    xs = {"fp64_jacobi_cg": (x64.cpu().numpy(), st64), "fp64_cg_fp32_pmg": (x32.cpu().numpy(), st32)}
+    M.close()
+    del x64, x32, b
+    print("oracle: assembled problem on the 32^3, N = 9 cube ...", flush=True)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    b_or = P.num.from_local_consistent(fld["b"])
+    b_or = b_or - b_or.mean()
+    sol = {}
+    for name, (xl, st) in xs.items():
+        xf = P.num.from_local_consistent(xl)
+        res = np.linalg.norm(b_or - P.apply(xf)) / np.linalg.norm(b_or)
+        sol[name] = xf
+        print(f"{name}: {st['iters']} it, oracle true res {res:.2e}, mean {xf.mean():.1e}",
+              flush=True)
+        assert st["converged"] == 1 and res <= 1.2e-10
+        assert abs(xf.mean()) <= 1e-13 * np.abs(xf).max()
+    print(f"x difference between the two: "
+          f"{rel(sol['fp64_cg_fp32_pmg'], sol['fp64_jacobi_cg']):.2e}", flush=True)
 
 
 @pytest.mark.parametrize("profile", [False, True])  # graph replay / eager launches
@@ -373,7 +473,7 @@ def test_pcg_first_kind_chebyshev_matches_oracle(precond_prec):
 
 
 @pytest.mark.parametrize("identify_interior", [False, True])
-def test_pcg_split_and_gather_paths_match_oracle(identify_interior):
+def test_pcg_split_and_gather_paths_match_oracle(identify_interior, store_form):
     # From N = 5 the in-solve operator writes single-copy nodes straight to the
     # free vector and shared copies to their element's surface slots.  A mesh
     # that identifies two element-interior nodes (valid: equal ids are one

@@ -193,6 +193,8 @@ def test_null_handles_are_rejected():
     assert lib.sem_ax(None, None, None, None, 0.0, 0, None) == L.SEM_EINVAL
     assert lib.sem_gs(None, None, 0, None) == L.SEM_EINVAL
     assert lib.sem_pcg_solve(None, None, None, None, 0.0, None, None, None) == L.SEM_EINVAL
+    assert lib.sem_solve_backward(None, None, None, None, 0.0, None, None, None, None,
+                                  None) == L.SEM_EINVAL
     assert lib.sem_free_mesh(None) == L.SEM_OK
     opts = L.SolveOpts()
     lib.sem_solve_opts_default(ctypes.byref(opts))
