@@ -13,8 +13,16 @@ bytes per local point (u, six geometric factors, w in FP64) per launch,
 divided by its average duration measured with HIP events on the solve's
 stream inside the timed region (around each operator launch of the last
 timed step; the other steps run without events).
-cpu_baseline: the CPU oracle's PCG iteration on a 32x8x16-element sample of
-the same recipe, timed on this host.
+CPU leg (after every GPU measurement): cpu_baseline, the CPU oracle's PCG
+iteration on a 32x8x16-element sample of the same recipe timed on this host;
+and the error of every solve result against the FP64 oracle: the GPU
+solutions are copied to the host after their timed solves, and the oracle's
+own operator gives their true residual ||b - A x|| / ||b|| (oracle_rel_res),
+with ||x - x_FP64|| / ||x_FP64|| against the FP64 Jacobi-CG solution of the
+same mesh (x_rel_diff_vs_fp64; on the 4^3 cubes against the oracle's own
+solution, x_rel_diff_vs_oracle) and, for the gradient workload, the oracle's
+residual of the adjoint solve and its k-gradient formed from the GPU's x and
+adjoint solution.
 """
 
 from __future__ import annotations
@@ -57,6 +65,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+class OracleChecks:
+    """GPU results kept on the host for the oracle's checks in the CPU leg:
+    per mesh (workload number, order, shape) the right-hand side and the
+    solution of every variant, and where each number goes in the JSON."""
+
+    def __init__(self):
+        self.meshes = {}
+
+    def add(self, key, spec, b_local, name, x_local, target):
+        ent = self.meshes.setdefault(key, dict(spec=spec, b=b_local, sols={}))
+        ent["sols"][name] = (x_local, target)
+
+
+CHECKS = OracleChecks()
+GRAD_CHECK = {}
+
+
 def cpu_baseline(iters):
     """The oracle as it stands: PCG iterations on a sample of the recipe."""
     import oracle
@@ -84,6 +109,63 @@ def cpu_baseline(iters):
                         f"{dt:.1f} s; its einsum/bincount kernels run on one thread "
                         f"({avail} cores available, {cpu})"),
                 seconds=dt)
+
+
+def oracle_errors(out):
+    """The FP64 oracle's verdict on every GPU solve result (CPU, untimed):
+    the true residual by the oracle's own assembled operator, the difference
+    to the FP64 Jacobi-CG solution of the same mesh (or, on the small cubes,
+    to the oracle's own solution at 1e-12), and for the gradient workload the
+    adjoint solve's residual and the k-gradient formed by the oracle from the
+    GPU's solution and adjoint solution."""
+    import oracle
+    from sem_inputs import config_mesh
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    for key, ent in CHECKS.meshes.items():
+        spec = ent["spec"]
+        t = time.time()
+        m, fld = config_mesh(spec["cfg"], N=spec.get("N"))
+        P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N, k=fld["k"], h2=fld["h2"])
+        if fld["f"] is not None:  # manufactured source: b = R Q^T (B f), f = 3 pi^2 u
+            b = P.rhs_from_source(fld["f"] * 3 * np.pi ** 2)
+        else:
+            b = P.num.from_local_consistent(ent["b"])
+        if P.neumann:
+            b = b - b.mean()
+        ref, ref_kind = None, None
+        if spec["cfg"] == 1:
+            ref, ref_kind = P.solve(b, rtol=1e-12)["x"], "x_rel_diff_vs_oracle"
+        elif "fp64_jacobi_cg" in ent["sols"]:
+            ref = P.num.from_local_consistent(ent["sols"]["fp64_jacobi_cg"][0])
+            ref_kind = "x_rel_diff_vs_fp64"
+        for name, (xl, target) in ent["sols"].items():
+            xf = P.num.from_local_consistent(xl)
+            target["oracle_rel_res"] = float(np.linalg.norm(b - P.apply(xf)) / np.linalg.norm(b))
+            if ref is not None and not (ref_kind == "x_rel_diff_vs_fp64"
+                                        and name == "fp64_jacobi_cg"):
+                target[ref_kind] = rel(xf, ref)
+        log(f"  {key}: {len(ent['sols'])} results checked in {time.time() - t:.1f}s")
+        del P, m, fld
+    if GRAD_CHECK:
+        g = GRAD_CHECK
+        m, fld = config_mesh(4)
+        P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N, k=fld["k"], h2=fld["h2"])
+        b = P.rhs_from_source(fld["f"])
+        xf = P.num.from_local_consistent(g["x"])
+        lf = P.num.from_local_consistent(g["lam"])
+        adj_b = P.num.R(P.num.Qt(g["xbar"]))
+        kb = -oracle.kgrad_contraction(P.num.to_local(xf), P.num.to_local(lf), P.G, m.N)
+        r = g["result"]
+        r["oracle_rel_res_forward"] = float(np.linalg.norm(b - P.apply(xf)) / np.linalg.norm(b))
+        r["oracle_rel_res_adjoint"] = float(np.linalg.norm(adj_b - P.apply(lf))
+                                            / np.linalg.norm(adj_b))
+        r["kbar_rel_diff_vs_oracle"] = rel(g["kbar"], kb)
+        r["kbar_autograd_rel_diff_vs_oracle"] = rel(g["kbar_autograd"], kb)
+        log(f"  gradient: forward res {r['oracle_rel_res_forward']:.2e}, adjoint res "
+            f"{r['oracle_rel_res_adjoint']:.2e}, kbar {r['kbar_rel_diff_vs_oracle']:.2e}")
 
 
 def ax_kernel_name(N):
@@ -139,7 +221,8 @@ def mixed_vs_fp64(sem, only=""):
 
     m, fld = config_mesh(5)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
-    b = torch.tensor(fld["b"], device="cuda")
+    b_host = fld["b"]
+    b = torch.tensor(b_host, device="cuda")
     del fld, m
     variants = {
         "fp64_jacobi_cg": dict(mode="cg", precond="jacobi"),
@@ -170,6 +253,7 @@ def mixed_vs_fp64(sem, only=""):
         out[name] = {"ms": st["time_ms"], "iters": st["iters"], "outer": st["outer_iters"],
                      "true_rel_res": res,
                      "gdof_s": M.info["n_unique"] * st["iters"] / (st["time_ms"] * 1e-3) / 1e9}
+        CHECKS.add("cube5", dict(cfg=5), b_host, name, x.cpu().numpy(), out[name])
         log(f"  {name}: {st['time_ms']:.1f} ms, {st['iters']} it, true rel res {res:.2e}")
     fp64 = ("fp64_jacobi_cg", "fp64_cheb3_fcg", "fp64_pmg_fcg", "fp64_pmg_jacobi_fcg")
     best = min((k for k in variants if k not in fp64
@@ -205,7 +289,7 @@ def pmg_setup(sem, M, b, name):
     M._bench_pmg_kind = kind
 
 
-def to_tolerance(sem, M, b):
+def to_tolerance(sem, M, b, b_host):
     """Time to ||b - A x|| <= 1e-10 ||b|| on the benchmark mesh: FP64 Jacobi
     CG against p-multigrid-preconditioned flexible CG (FP64 and FP32 cycles)
     and refinement around it."""
@@ -223,6 +307,7 @@ def to_tolerance(sem, M, b):
         x, st = sem.solve(M, b, rtol=1e-10, max_iter=30000, **v)
         out[name] = {"ms": st["time_ms"], "iters": st["iters"], "outer": st["outer_iters"],
                      "true_rel_res": true_rel_residual(sem, M, b, x)}
+        CHECKS.add("box2", dict(cfg=2), b_host, name, x.cpu().numpy(), out[name])
         log(f"  {name}: {st['time_ms']:.1f} ms, {st['iters']} it, "
             f"true rel res {out[name]['true_rel_res']:.2e}")
     return out
@@ -341,6 +426,7 @@ def small_solves(sem):
             x, st = best
             res[name] = {"ms": st["time_ms"], "iters": st["iters"], "outer": st["outer_iters"],
                          "true_rel_res": true_rel_residual(sem, M, b, x)}
+            CHECKS.add(f"cube1_N{N}", dict(cfg=1, N=N), None, name, x.cpu().numpy(), res[name])
         out[f"N{N}"] = res
         M.close()
     return out
@@ -374,6 +460,15 @@ def gradient_timing(sem):
         t2 = time.perf_counter()
         out = {"forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
                "n_unique": M.info["n_unique"]}
+    # for the oracle's checks (untimed): the cotangent autograd passes,
+    # dL/dx = 2 w (x - target), and the adjoint solution lam = bbar x copies
+    xd = x.detach()
+    xbar = (2.0 * w * (xd - target)).contiguous()
+    kbar, bbar, _ = sem.solve_backward(M, xd, xbar, k=k0, h2=fld["h2"], rtol=1e-12,
+                                       max_iter=20000)
+    GRAD_CHECK.update(x=xd.cpu().numpy(), xbar=xbar.cpu().numpy(),
+                      lam=(bbar * free).cpu().numpy(), kbar=kbar.cpu().numpy(),
+                      kbar_autograd=k.grad.detach().cpu().numpy(), result=out)
     M.close()
     return out
 
@@ -396,7 +491,8 @@ def main():
     t = time.time()
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
     log(f"setup in {time.time() - t:.1f}s: {M.info}")
-    b = torch.tensor(fld["b"], device="cuda")
+    b_host = fld["b"]
+    b = torch.tensor(b_host, device="cuda")
     del fld
     x = torch.zeros_like(b)
     n_unique = M.info["n_unique"]
@@ -519,7 +615,7 @@ def main():
     }
     if not args.no_extras:
         log("to 1e-10 on the benchmark mesh ...")
-        out["to_tolerance"] = to_tolerance(sem, M, b)
+        out["to_tolerance"] = to_tolerance(sem, M, b, b_host)
         M.close()
         log("small solves (4^3 unit cube, N = 7 and 9) ...")
         out["small_solves"] = small_solves(sem)
@@ -535,6 +631,10 @@ def main():
         cb = cpu_baseline(args.cpu_sample_iters)
         cb.pop("seconds", None)
         out["cpu_baseline"] = cb
+        log("oracle errors of the solve results ...")
+        t = time.time()
+        oracle_errors(out)
+        log(f"oracle errors in {time.time() - t:.1f}s")
     print(json.dumps(out), flush=True)
 
 
