@@ -438,62 +438,94 @@ static sem_status solve_free(const sem_mesh* m, const double* k, double h2,
   double rel = 0.0;
 
   if (opts.mode == SEM_SOLVE_CG) {
-    CgArgs<double, double> a;
-    a.op = op64;
-    a.b = bf;
-    a.x = xf;
-    a.r = W.vec<double>(W.r, nf);
-    a.p = W.vec<double>(W.p, nf);
-    a.w = W.vec<double>(W.w, nf);
-    a.z = W.vec<double>(W.z, nf);
-    a.wL = W.vec<double>(W.wL, m->nL);
-    if (!a.r || !a.p || !a.w || !a.z || !a.wL) return fail(SEM_ENOMEM, "work space");
-    a.dinv = dinv;
-    a.precond = opts.precond;
-    a.cheb_order = opts.cheb_order;
-    if (pmg) {
-      if (pmg64)
-        a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
-                    const ChebCg& cg, hipStream_t ss, int* ap) {
-          return pmg_precond<double, double>(mm, WW, r, z, cg, ss, ap);
-        };
-      else
-        a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
-                    const ChebCg& cg, hipStream_t ss, int* ap) {
-          return pmg_precond<double, float>(mm, WW, r, z, cg, ss, ap);
-        };
-    } else if (cheb) {
-      const int order = opts.cheb_order;
-      if (opts.precond_prec == SEM_FP64) {
-        a.cheb = [op64, dinv, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                           double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, cg, ss, ap,
-                                                kind);
-        };
-      } else {
-        a.cheb = [opc, dinv32, order, lmax, kind](const sem_mesh* mm, SolveWork& WW, const double* r,
-                                            double* z, const ChebCg& cg, hipStream_t ss, int* ap) {
-          return cheb_apply_dev<double, float>(mm, WW, opc, dinv32, r, z, order, lmax, cg, ss, ap,
-                                               kind);
-        };
+    // A Chebyshev preconditioner of order >= 2 with FP64 or FP32 contractions
+    // runs inside the CG's own kernels when the split operator is available
+    // (the CG then carries the preconditioner's precision as Tp); z_0 = M r_0
+    // still comes from the stand-alone pass.
+    const bool fuse = cheb && opts.cheb_order >= 2 && ax_split_available(m) &&
+                      (opts.precond_prec == SEM_FP64 || opts.precond_prec == SEM_FP32);
+    auto run = [&](auto& a) -> sem_status {
+      a.op = op64;
+      a.b = bf;
+      a.x = xf;
+      a.r = W.vec<double>(W.r, nf);
+      a.p = W.vec<double>(W.p, nf);
+      a.w = W.vec<double>(W.w, nf);
+      a.z = W.vec<double>(W.z, nf);
+      a.wL = W.vec<double>(W.wL, m->nL);
+      if (!a.r || !a.p || !a.w || !a.z || !a.wL) return fail(SEM_ENOMEM, "work space");
+      a.dinv = dinv;
+      a.precond = opts.precond;
+      a.cheb_order = opts.cheb_order;
+      if (pmg) {
+        if (pmg64)
+          a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
+                      const ChebCg& cg, hipStream_t ss, int* ap) {
+            return pmg_precond<double, double>(mm, WW, r, z, cg, ss, ap);
+          };
+        else
+          a.cheb = [](const sem_mesh* mm, SolveWork& WW, const double* r, double* z,
+                      const ChebCg& cg, hipStream_t ss, int* ap) {
+            return pmg_precond<double, float>(mm, WW, r, z, cg, ss, ap);
+          };
+      } else if (cheb) {
+        const int order = opts.cheb_order;
+        if (opts.precond_prec == SEM_FP64) {
+          a.cheb = [op64, dinv, order, lmax, kind](const sem_mesh* mm, SolveWork& WW,
+                                                   const double* r, double* z, const ChebCg& cg,
+                                                   hipStream_t ss, int* ap) {
+            return cheb_apply_dev<double, double>(mm, WW, op64, dinv, r, z, order, lmax, cg, ss,
+                                                  ap, kind);
+          };
+        } else {
+          a.cheb = [opc, dinv32, order, lmax, kind](const sem_mesh* mm, SolveWork& WW,
+                                                    const double* r, double* z, const ChebCg& cg,
+                                                    hipStream_t ss, int* ap) {
+            return cheb_apply_dev<double, float>(mm, WW, opc, dinv32, r, z, order, lmax, cg, ss,
+                                                 ap, kind);
+          };
+        }
       }
+      a.rtol = opts.rtol;
+      a.max_it = opts.max_iter;
+      a.fixed = opts.fixed_iters != 0;
+      a.x_zero = x_zero;
+      a.neumann = neumann;
+      a.profile = opts.profile != 0;
+      a.check_every = opts.check_every;
+      if (pmg) a.max_chunk = kPmgMaxChunk;
+      a.hist = opts.residual_history;
+      CgResult res;
+      sem_status sst = cg_solve(m, W, a, res, s);
+      if (sst) return sst;
+      iters = res.iters;
+      applies = res.applies;
+      converged = res.converged;
+      fail_status = res.status;
+      rel = res.bnorm > 0.0 ? res.rnorm / res.bnorm : 0.0;
+      return SEM_OK;
+    };
+    if (fuse && opts.precond_prec == SEM_FP32) {
+      CgArgs<double, float> a;
+      a.fuse.on = true;
+      a.fuse.op = opc;
+      a.fuse.dinv = dinv32;
+      a.fuse.order = opts.cheb_order;
+      a.fuse.lmax = lmax;
+      a.fuse.kind = kind;
+      if ((st = run(a))) return st;
+    } else {
+      CgArgs<double, double> a;
+      if (fuse) {
+        a.fuse.on = true;
+        a.fuse.op = op64;
+        a.fuse.dinv = dinv;
+        a.fuse.order = opts.cheb_order;
+        a.fuse.lmax = lmax;
+        a.fuse.kind = kind;
+      }
+      if ((st = run(a))) return st;
     }
-    a.rtol = opts.rtol;
-    a.max_it = opts.max_iter;
-    a.fixed = opts.fixed_iters != 0;
-    a.x_zero = x_zero;
-    a.neumann = neumann;
-    a.profile = opts.profile != 0;
-    a.check_every = opts.check_every;
-    if (pmg) a.max_chunk = kPmgMaxChunk;
-    a.hist = opts.residual_history;
-    CgResult res;
-    if ((st = cg_solve<double, double>(m, W, a, res, s))) return st;
-    iters = res.iters;
-    applies = res.applies;
-    converged = res.converged;
-    fail_status = res.status;
-    rel = res.bnorm > 0.0 ? res.rnorm / res.bnorm : 0.0;
   } else {
     // FP64 iterative refinement around an FP32 inner CG
     double* r = W.vec<double>(W.r, nf);
@@ -524,6 +556,14 @@ static sem_status solve_free(const sem_mesh* m, const double* k, double h2,
         return cheb_apply_dev<float, float>(mm, WW, opc, dinv32, rr, z, order, lmax, cg, ss, ap,
                                             kind);
       };
+      if (order >= 2 && opc.lp == 0 && ax_split_available(m)) {
+        a.fuse.on = true;
+        a.fuse.op = opc;
+        a.fuse.dinv = dinv32;
+        a.fuse.order = order;
+        a.fuse.lmax = lmax;
+        a.fuse.kind = kind;
+      }
     }
     a.neumann = neumann;
     a.x_zero = true;

@@ -259,8 +259,9 @@ hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, c
 // vector), at shared free nodes to wL at e P + surface_rank (local, for the
 // segmented sum over [n_single, n_free) through fperm2); epart[3 (parts e +
 // i) + {0, 1, 2}] (parts = ax_split_parts(N), one per wavefront i) = the
-// sums of u w, w and u over the single-copy nodes.  hipErrorNotSupported
-// when unavailable (see ax_split_available).
+// sums of u w, w and u over the single-copy nodes (nullable: then no sums
+// are formed).  hipErrorNotSupported when unavailable (see
+// ax_split_available).
 template <typename T>
 hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart,
                            const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,

@@ -334,7 +334,9 @@ struct MShape {
 // wave) + a] receives each wavefront's sums of p w and w over all its free
 // copies and of p over its single-copy nodes (p = the gathered input),
 // reduced in a fixed order.  MODE 3: MODE 2 with nontemporal shared-copy
-// stores (for local arrays larger than the memory-side cache).
+// stores (for local arrays larger than the memory-side cache).  MODE 4 / 5:
+// MODE 2 / 3 without the wavefront sums (a Chebyshev pass needs none; they
+// cost the FP32 N = 9 operator 10 %).
 // Waves per SIMD the split in-solve form asks for: the gather form's
 // occupancy at N = 6 and N = 9, which a few extra registers would cost it
 // (at N = 9, with 512-thread workgroups, one fewer resident workgroup per CU
@@ -352,6 +354,8 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
   constexpr int n1 = S::n1, P = S::P, TPB = S::TPB, PPT = S::PPT, NT = S::NT, KS = S::KS,
                 NW = S::NW;
   static_assert(LP == 0 || std::is_same<T, float>::value, "16-bit operands need FP32 data");
+  constexpr bool kDots = (MODE == 2 || MODE == 3);       // wavefront sums into epart
+  constexpr bool kNtShared = (MODE == 3 || MODE == 5);   // nontemporal shared-copy stores
   constexpr bool kScale = LP == 2;
   if (skip && *skip) return;  // uniform over the grid
   __shared__ T su[P];
@@ -536,27 +540,31 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
         const int32_t c = scode[q];
         if (c >= 0) {
           st_stream(acc, wf + c);
-          ps[0] += (double)uq[s] * (double)acc;
-          ps[1] += (double)acc;
-          ps[2] += (double)uq[s];
+          if constexpr (kDots) {
+            ps[0] += (double)uq[s] * (double)acc;
+            ps[1] += (double)acc;
+            ps[2] += (double)uq[s];
+          }
         } else if (c <= -2) {
           // shared copy: at its surface slot of the element's block.  Its
           // share of p.w and sum(w): over all copies these add up to p_g w_g
           // and w_g (sum(p) over the shared nodes is left to the segmented sum)
           T* dst = w + e * P + surface_rank(q % n1, (q / n1) % n1, q / (n1 * n1), N);
-          if constexpr (MODE == 2)
-            *dst = acc;
-          else
+          if constexpr (kNtShared)
             st_stream(acc, dst);
-          ps[0] += (double)uq[s] * (double)acc;
-          ps[1] += (double)acc;
+          else
+            *dst = acc;
+          if constexpr (kDots) {
+            ps[0] += (double)uq[s] * (double)acc;
+            ps[1] += (double)acc;
+          }
         }
       } else {
         st_stream(acc, w + idx);
       }
     }
   }
-  if constexpr (MODE >= 2) {
+  if constexpr (kDots) {
     // one triple of sums per wavefront: no barrier, no LDS.  Lane 0 is found
     // by mbcnt here rather than from the lane index computed at the start,
     // which the compiler would otherwise keep (and at N = 9 spill) all along.
@@ -748,11 +756,19 @@ hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epa
     // 1.1 % faster per iteration), nontemporal above (the 32^3, N = 9 cube:
     // 262 MB, 2.2 %) (MODE 2 plain, MODE 3 nontemporal: a run-time switch in
     // the kernel cost what the nontemporal stores save)
-    if (m->nL * (int64_t)sizeof(T) <= m->ax_nt_bytes)
+    // without epart: the forms without wavefront sums (MODE 4 / 5)
+    const bool plain = m->nL * (int64_t)sizeof(T) <= m->ax_nt_bytes;
+    if (epart && plain)
       hipLaunchKernelGGL((ax_mfma_kernel<N, T, 2, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
                          u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
-    else
+    else if (epart)
       hipLaunchKernelGGL((ax_mfma_kernel<N, T, 3, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                         u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+    else if (plain)
+      hipLaunchKernelGGL((ax_mfma_kernel<N, T, 4, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
+                         u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+    else
+      hipLaunchKernelGGL((ax_mfma_kernel<N, T, 5, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
                          u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
     return hipGetLastError();
   } else {

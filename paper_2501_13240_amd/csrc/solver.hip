@@ -179,6 +179,41 @@ __device__ __forceinline__ bool aligned16(const void* a, const void* b, const vo
   return (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) == 0;
 }
 
+// alpha = rho / (p.w - mean_w sum(p)) from the p.w, sum(w), sum(p) partials,
+// the same in every block; block 0 records alpha, mean_w and the iteration in
+// progress (the iteration index lives on the device, so a captured chunk of
+// iterations can be replayed: only later kernels advance it).  False on a
+// breakdown (p.w <= 0 or not finite), which ends the solve.
+__device__ __forceinline__ bool cg_alpha(const double* __restrict__ part_in, int nblk,
+                                         CgScalars* __restrict__ sc, double* __restrict__ ahist,
+                                         bool set_pending, double& alpha, double& mw) {
+  const int kit = sc->it;
+  double S[3];
+  block_total<3>(part_in, nblk, S);
+  double pw = S[0];
+  mw = 0.0;
+  if (sc->neumann) {
+    mw = S[1] * sc->inv_n;
+    pw -= mw * S[2];
+  }
+  if (!(pw > 0.0) || !finite(pw)) {  // same decision in every block
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->status = 2;
+      sc->done = 1;
+    }
+    return false;
+  }
+  alpha = sc->rho2[kit & 1] / pw;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->alpha = alpha;
+    sc->mean_w = mw;
+    sc->kcur = kit;
+    if (set_pending) sc->pending = 1;
+    if (ahist) ahist[kit] = alpha;
+  }
+  return true;
+}
+
 // alpha from the p.w partials; x += alpha p (not kUpdJacZ);
 // r -= alpha (w - mean_w); partials of r.r (and r.S r)
 template <typename T, int MODE>
@@ -191,31 +226,8 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
                                                       CgScalars* __restrict__ sc,
                                                       double* __restrict__ ahist) {
   if (sc->done) return;
-  // the iteration index lives on the device (so a captured chunk of
-  // iterations can be replayed): it is only advanced by later kernels
-  const int kit = sc->it;
-  double S[3];
-  block_total<3>(part_in, nblk, S);
-  double pw = S[0], mw = 0.0;
-  if (sc->neumann) {
-    mw = S[1] * sc->inv_n;
-    pw -= mw * S[2];
-  }
-  if (!(pw > 0.0) || !finite(pw)) {  // same decision in every block
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->status = 2;
-      sc->done = 1;
-    }
-    return;
-  }
-  const double alpha = sc->rho2[kit & 1] / pw;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->alpha = alpha;
-    sc->mean_w = mw;
-    sc->kcur = kit;
-    if (MODE == kUpdJacZ) sc->pending = 1;
-    if (ahist) ahist[kit] = alpha;
-  }
+  double alpha, mw;
+  if (!cg_alpha(part_in, nblk, sc, ahist, MODE == kUpdJacZ, alpha, mw)) return;
   const T a = (T)alpha, mwt = (T)mw;
   double v[2] = {0.0, 0.0};
   if constexpr (MODE == kUpdJacZ) {
@@ -334,9 +346,9 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __rest
 
 // flexible CG: beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha z.(w - mean_w) / rho_k
 // from the preconditioner pass's partials (z.r, z.(w - mean_w)); p = z + beta p
-template <typename T>
+template <typename T, typename Tz>
 __global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, T* __restrict__ p,
-                                                            const T* __restrict__ z,
+                                                            const Tz* __restrict__ z,
                                                             const double* __restrict__ part_in,
                                                             int nblk, CgScalars* __restrict__ sc,
                                                             double* __restrict__ bhist) {
@@ -359,7 +371,7 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, T* __res
     if (bhist) bhist[kit] = beta;
   }
   const T b = (T)beta;
-  BLOCK_CHUNK(g, nf) p[g] = z[g] + b * p[g];
+  BLOCK_CHUNK(g, nf) p[g] = (T)z[g] + b * p[g];
 }
 
 // ----------------------------------------------------- init / misc kernels
@@ -525,6 +537,92 @@ __global__ __launch_bounds__(kVecBlock) void k_cheb_step(
     }
   }
   if constexpr (DOTS) block_partials<2>(v, part);
+}
+
+// ------------------------------------------ Chebyshev fused into the CG
+//
+// Inside a flexible CG whose preconditioner is Chebyshev of order m >= 2 on
+// the split operator (the in-solve operator form, in the preconditioner's
+// precision Tp), the pass runs in the CG's own kernels:
+//   update:  alpha; x += alpha p; r -= alpha (w - mean_w); r.r partials; and
+//            d_0 = c0 S r (no separate start kernel, r itself serves as r_0);
+//   step k:  s = R Q^T A d_{k-1}, read at the single-copy nodes from the
+//            operator's free-vector output and summed over the surface slots
+//            at the shared ones; r_k = r_{k-1} - s; d_k = a_k d_{k-1} + b_k S r_k;
+//            z_k = z_{k-1} + d_k (z_0 = d_0);
+// the first step takes the convergence decision on the update's r.r
+// partials, the last one writes z in Tp (not r_m, d_m) with the z.r and
+// z.(w - mean_w) partials for beta.  z is formed in Tp arithmetic anyway,
+// so storing it in Tp loses nothing.
+
+// alpha; x += alpha p; r -= alpha (w - mean_w); partials of r.r; d0 = c0 S r
+template <typename T, typename Tp>
+__global__ __launch_bounds__(kVecBlock) void k_update_cheb0(
+    int64_t nf, T* __restrict__ x, const T* __restrict__ p, T* __restrict__ r,
+    const T* __restrict__ w, const Tp* __restrict__ sinv, Tp* __restrict__ d0, double c0,
+    const double* __restrict__ part_in, int nblk, double* __restrict__ part,
+    CgScalars* __restrict__ sc, double* __restrict__ ahist) {
+  if (sc->done) return;
+  double alpha, mw;
+  if (!cg_alpha(part_in, nblk, sc, ahist, false, alpha, mw)) return;
+  const T a = (T)alpha, mwt = (T)mw;
+  const Tp c = (Tp)c0;
+  double v[2] = {0.0, 0.0};
+  BLOCK_CHUNK(g, nf) {
+    x[g] = x[g] + a * p[g];
+    const T rg = r[g] - a * (w[g] - mwt);
+    r[g] = rg;
+    d0[g] = c * sinv[g] * (Tp)rg;
+    const double rd = (double)rg;
+    v[0] += rd * rd;
+  }
+  block_partials<2>(v, part);
+}
+
+// one step of the fused pass (see above); FIRST: r_{k-1} = r (type T) and
+// z_{k-1} = d_{k-1}, and the convergence gate; LAST: z_k to z, partials of
+// z.r and z.(w - mean_w)
+template <typename T, typename Tp, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kVecBlock) void k_cheb_fstep(
+    int64_t n1, int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
+    const Tp* __restrict__ wf, const Tp* __restrict__ wL, const T* __restrict__ r,
+    Tp* __restrict__ rk, Tp* __restrict__ d, const Tp* __restrict__ sinv, Tp* __restrict__ za,
+    Tp* __restrict__ z, const T* __restrict__ w, double ca, double cb,
+    const double* __restrict__ check_in, int nblk, double* __restrict__ part,
+    CgScalars* __restrict__ sc, double* __restrict__ hist) {
+  if (sc->done) return;
+  if (FIRST && !cheb_gate<true>(check_in, nblk, sc, hist)) return;
+  const double mw = LAST ? sc->mean_w : 0.0;
+  const Tp a = (Tp)ca, b = (Tp)cb;
+  double v[2] = {0.0, 0.0};
+  auto step = [&](int64_t g, Tp s) {
+    const Tp rprev = FIRST ? (Tp)r[g] : rk[g];
+    const Tp dprev = d[g];
+    const Tp rkg = rprev - s;
+    const Tp dg = a * dprev + b * sinv[g] * rkg;
+    const Tp zg = (FIRST ? dprev : za[g]) + dg;
+    if constexpr (LAST) {
+      z[g] = zg;
+      v[0] += (double)zg * (double)r[g];
+      v[1] += (double)zg * ((double)w[g] - mw);
+    } else {
+      rk[g] = rkg;
+      d[g] = dg;
+      za[g] = zg;
+    }
+  };
+  // every block takes a chunk of the single-copy nodes [0, n1) and one of the
+  // shared nodes [n1, nf), so the segmented sums are spread over all blocks
+  {
+    BLOCK_CHUNK(g, n1) step(g, wf[g]);
+  }
+  {
+    BLOCK_CHUNK(i, nf - n1) {
+      const int64_t g = n1 + i;
+      step(g, segment_sum<Tp>(perm, wL, seg[g], seg[g + 1]));
+    }
+  }
+  if constexpr (LAST) block_partials<2>(v, part);
 }
 
 // ------------------------------------------- fixed-count CG on the device
@@ -751,25 +849,56 @@ template sem_status apply_op<float>(const sem_mesh*, SolveWork&, const Op<float>
 
 // ------------------------------------------------------ Chebyshev on device
 
-template <typename Tr, typename Tp>
-sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
-                          const Tr* r, Tr* z, int order, double lmax, const ChebCg& cg,
-                          hipStream_t s, int* applies, int kind) {
-  const int64_t nf = m->n_free;
-  const unsigned nb = vgrid(nf);
-  Tp* d = W.vec<Tp>(sizeof(Tp) == 8 ? W.cd : W.cd32, nf);
-  Tp* rk = W.vec<Tp>(sizeof(Tp) == 8 ? W.crk : W.crk32, nf);
-  Tp* wL = W.vec<Tp>(sizeof(Tp) == 8 ? W.wL : W.wL32, m->nL);
-  if (!d || !rk || !wL) return fail(SEM_ENOMEM, "Chebyshev work space");
-  const bool flex = cg.sc != nullptr;
-  const Tr* wcg = static_cast<const Tr*>(cg.w);
-  // fourth kind (default) or first kind on [lmax/10, lmax]: the kernels take
-  // d = c0 S r, then d = ca d + cb S r_k; only the coefficients differ
+// fourth kind (default) or first kind on [lmax/10, lmax]: the kernels take
+// d = c0 S r, then d = ca d + cb S r_k; only the coefficients differ
+void cheb_coeffs(int order, double lmax, int kind, double* c0, std::vector<double>& ca,
+                 std::vector<double>& cb) {
   const bool first = (kind == 1);
   const double lo = lmax / 10.0, theta = 0.5 * (lmax + lo), delta = 0.5 * (lmax - lo);
   const double sigma = theta / delta;
   double rho_prev = 1.0 / sigma;
-  const double c0 = first ? 1.0 / theta : 4.0 / (3.0 * lmax);
+  *c0 = first ? 1.0 / theta : 4.0 / (3.0 * lmax);
+  ca.assign(std::max(order, 1), 0.0);
+  cb.assign(std::max(order, 1), 0.0);
+  for (int k = 1; k < order; ++k) {
+    if (first) {
+      const double rho = 1.0 / (2.0 * sigma - rho_prev);
+      ca[k] = rho * rho_prev;
+      cb[k] = 2.0 * rho / delta;
+      rho_prev = rho;
+    } else {
+      ca[k] = (2.0 * k - 1.0) / (2.0 * k + 3.0);
+      cb[k] = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
+    }
+  }
+}
+
+template <typename Tr, typename Tp>
+sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
+                          const Tr* r, Tr* z, int order, double lmax, const ChebCg& cg,
+                          hipStream_t s, int* applies, int kind) {
+  ChebBufs<Tp> b;
+  b.d = W.vec<Tp>(sizeof(Tp) == 8 ? W.cd : W.cd32, m->n_free);
+  b.rk = W.vec<Tp>(sizeof(Tp) == 8 ? W.crk : W.crk32, m->n_free);
+  b.wL = W.vec<Tp>(sizeof(Tp) == 8 ? W.wL : W.wL32, m->nL);
+  if (!b.d || !b.rk || !b.wL) return fail(SEM_ENOMEM, "Chebyshev work space");
+  return cheb_apply_bufs<Tr, Tp>(m, op, dinv, r, z, order, lmax, cg, s, applies, kind, b);
+}
+
+template <typename Tr, typename Tp>
+sem_status cheb_apply_bufs(const sem_mesh* m, const Op<Tp>& op, const Tp* dinv, const Tr* r,
+                           Tr* z, int order, double lmax, const ChebCg& cg, hipStream_t s,
+                           int* applies, int kind, const ChebBufs<Tp>& b) {
+  const int64_t nf = m->n_free;
+  const unsigned nb = vgrid(nf);
+  Tp* d = b.d;
+  Tp* rk = b.rk;
+  Tp* wL = b.wL;
+  const bool flex = cg.sc != nullptr;
+  const Tr* wcg = static_cast<const Tr*>(cg.w);
+  double c0;
+  std::vector<double> cav, cbv;
+  cheb_coeffs(order, lmax, kind, &c0, cav, cbv);
   Op<Tp> opk = op;
   if (flex) opk.skip = &cg.sc->done;
   else if (cg.skip_sc) opk.skip = &cg.skip_sc->done;
@@ -788,19 +917,11 @@ sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, con
                        cg.hist);
   SEM_CHECK_LAUNCH("Chebyshev init");
   for (int k = 1; k < order; ++k) {
-    sem_status st = apply_op<Tp>(m, W, opk, d, wL, s, false);
-    if (st) return st;
+    const hipError_t e = launch_ax<Tp>(m, d, m->lmap.as<int32_t>(), wL, opk.k, opk.h2, opk.G,
+                                       opk.B, opk.D, s, opk.skip, opk.lp);
+    if (e != hipSuccess) return hip_fail(e, "operator kernel");
     if (applies) ++*applies;
-    double ca, cb;
-    if (first) {
-      const double rho = 1.0 / (2.0 * sigma - rho_prev);
-      ca = rho * rho_prev;
-      cb = 2.0 * rho / delta;
-      rho_prev = rho;
-    } else {
-      ca = (2.0 * k - 1.0) / (2.0 * k + 3.0);
-      cb = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
-    }
+    const double ca = cav[k], cb = cbv[k];
     if (flex && k == order - 1)
       hipLaunchKernelGGL((k_cheb_step<Tp, Tr, true>), dim3(nb), dim3(kVecBlock), 0, s, nf,
                          m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, d, dinv, z, ca, cb,
@@ -822,6 +943,14 @@ template sem_status cheb_apply_dev<double, float>(const sem_mesh*, SolveWork&, c
 template sem_status cheb_apply_dev<float, float>(const sem_mesh*, SolveWork&, const Op<float>&,
                                                  const float*, const float*, float*, int, double,
                                                  const ChebCg&, hipStream_t, int*, int);
+template sem_status cheb_apply_bufs<double, double>(const sem_mesh*, const Op<double>&,
+                                                    const double*, const double*, double*, int,
+                                                    double, const ChebCg&, hipStream_t, int*, int,
+                                                    const ChebBufs<double>&);
+template sem_status cheb_apply_bufs<double, float>(const sem_mesh*, const Op<float>&,
+                                                   const float*, const double*, double*, int,
+                                                   double, const ChebCg&, hipStream_t, int*, int,
+                                                   const ChebBufs<float>&);
 
 // ------------------------------------------------------------------- CG
 
@@ -923,6 +1052,46 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   const int64_t nparts = split ? m->E * ax_split_parts(m->N) : 0;
   double* epart = split ? W.vec<double>(W.epart, 3 * nparts) : nullptr;
   if (split && !epart) return fail(SEM_ENOMEM, "work space");
+  // Chebyshev fused into the iteration's kernels (needs the split operator)
+  const ChebFuse<Tp>& fu = a.fuse;
+  const bool fused = !jac && fu.on && split && fu.order >= 2 && fu.op.lp == 0;
+  Op<Tp> fop = fu.op;
+  fop.skip = &sc->done;
+  Tp *fd = nullptr, *frk = nullptr, *fwf = nullptr, *fza = nullptr, *fz = nullptr, *fwL = nullptr;
+  double fc0 = 0.0;
+  std::vector<double> fca, fcb;
+  if (fused) {
+    fd = W.vec<Tp>(sizeof(Tp) == 8 ? W.cd : W.cd32, nf);
+    frk = W.vec<Tp>(sizeof(Tp) == 8 ? W.crk : W.crk32, nf);
+    fwf = W.vec<Tp>(W.cwf, nf);
+    fza = W.vec<Tp>(W.cza, nf);
+    fz = W.vec<Tp>(W.cz, nf);
+    fwL = W.vec<Tp>(sizeof(Tp) == 8 ? W.wL : W.wL32, m->nL);
+    if (!fd || !frk || !fwf || !fza || !fz || !fwL) return fail(SEM_ENOMEM, "Chebyshev work space");
+    cheb_coeffs(fu.order, fu.lmax, fu.kind, &fc0, fca, fcb);
+  }
+  auto fused_pass = [&](hipStream_t ss) -> sem_status {
+    hipLaunchKernelGGL((k_update_cheb0<T, Tp>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
+                       fu.dinv, fd, fc0, partA, (int)nb, partB, sc, ahist);
+    for (int k = 1; k < fu.order; ++k) {
+      const hipError_t he = launch_ax_split<Tp>(m, fd, fwf, fwL, nullptr, fop.k, fop.h2, fop.G,
+                                                fop.B, fop.D, ss, fop.skip);
+      if (he != hipSuccess) return hip_fail(he, "Chebyshev operator");
+      const bool first = (k == 1), last = (k == fu.order - 1);
+#define SEM_FSTEP(F, L)                                                                        \
+  hipLaunchKernelGGL((k_cheb_fstep<T, Tp, F, L>), dim3(nb), dim3(kVecBlock), 0, ss, m->n_single, \
+                     nf, m->fseg.as<int32_t>(), m->fperm2.as<int32_t>(), fwf, fwL, r, frk, fd,    \
+                     fu.dinv, fza, fz, w, fca[k], fcb[k], partB, (int)nb, partC, sc, hist)
+      if (first && last) SEM_FSTEP(true, true);
+      else if (first) SEM_FSTEP(true, false);
+      else if (last) SEM_FSTEP(false, true);
+      else SEM_FSTEP(false, false);
+#undef SEM_FSTEP
+    }
+    hipLaunchKernelGGL((k_pupdate_flex<T, Tp>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, fz,
+                       partC, (int)nb, sc, bhist);
+    return SEM_OK;
+  };
   auto iteration = [&](hipStream_t ss) -> sem_status {
     sem_status e;
     if (split) {
@@ -940,6 +1109,8 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
                          w, a.dinv, partA, (int)nb, partB, sc, ahist);
       hipLaunchKernelGGL((k_pupdate_jac<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, x, r,
                          a.dinv, partB, (int)nb, sc, hist, bhist);
+    } else if (fused) {
+      if ((e = fused_pass(ss))) return e;
     } else {
       hipLaunchKernelGGL((k_update<T, kUpdR>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
                          a.dinv, partA, (int)nb, partB, sc, ahist);
@@ -951,7 +1122,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
       cg.part_out = partC;
       cg.hist = hist;
       if ((e = a.cheb(m, W, r, z, cg, ss, nullptr))) return e;
-      hipLaunchKernelGGL((k_pupdate_flex<T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, z, partC,
+      hipLaunchKernelGGL((k_pupdate_flex<T, T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, z, partC,
                          (int)nb, sc, bhist);
     }
     SEM_CHECK_LAUNCH("CG iteration");

@@ -14,6 +14,8 @@ struct SolveWork {
   DevBuf bf, x, r, p, w, z, wL, dinv, tmpf;          // FP64
   DevBuf x32, r32, ri32, p32, w32, z32, wL32, dinv32, k32; // FP32
   DevBuf cd, crk, cd32, crk32;                       // Chebyshev d and r_k
+  DevBuf cwf, cza, cz;                               // fused Chebyshev: A d at single-copy
+                                                     // nodes, running z, output z
   DevBuf part, sc, red, hist, ahist, bhist, epart;
   CgScalars* h_sc = nullptr;  // pinned: [0..1] polling slots, [3] upload
   double* h_red = nullptr;    // pinned reduction results
@@ -66,6 +68,23 @@ template <typename T>
 using ChebFn = std::function<sem_status(const sem_mesh*, SolveWork&, const T* r, T* z,
                                         const ChebCg& cg, hipStream_t s, int* applies)>;
 
+// Chebyshev preconditioner of order >= 2 run inside the flexible CG's own
+// kernels on the split operator in precision Tp (see k_update_cheb0); when
+// `on`, the iterations use it and `cheb` only forms z_0 = M r_0
+template <typename Tp>
+struct ChebFuse {
+  bool on = false;
+  Op<Tp> op;
+  const Tp* dinv = nullptr;
+  int order = 3;
+  double lmax = 0.0;
+  int kind = 4;  // 4: fourth kind, 1: first kind on [lmax / 10, lmax]
+};
+
+// coefficients of a Chebyshev pass: d_0 = c0 S r, d_k = ca[k] d_{k-1} + cb[k] S r_k
+void cheb_coeffs(int order, double lmax, int kind, double* c0, std::vector<double>& ca,
+                 std::vector<double>& cb);
+
 template <typename T, typename Tp>
 struct CgArgs {
   Op<T> op;
@@ -75,6 +94,7 @@ struct CgArgs {
   int precond = SEM_PRECOND_JACOBI;
   int cheb_order = 3;
   ChebFn<T> cheb;
+  ChebFuse<Tp> fuse;
   double rtol = 1e-10;
   int max_it = 1000;
   bool fixed = false;
@@ -96,10 +116,24 @@ template <typename T>
 sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* xf, T* wL,
                     hipStream_t s, bool timed, T* wf = nullptr, double* epart = nullptr);
 
+// work vectors of one Chebyshev pass: d, r_k (free, n_free) and w_L (local, n_L)
+template <typename Tp>
+struct ChebBufs {
+  Tp* d = nullptr;
+  Tp* rk = nullptr;
+  Tp* wL = nullptr;
+};
+
+// z = p_m(S A) S r with the work vectors taken from the mesh's work space
 template <typename Tr, typename Tp>
 sem_status cheb_apply_dev(const sem_mesh* m, SolveWork& W, const Op<Tp>& op, const Tp* dinv,
                           const Tr* r, Tr* z, int order, double lmax, const ChebCg& cg,
                           hipStream_t s, int* applies, int kind = 4);
+// the same with caller-provided work vectors (no allocation)
+template <typename Tr, typename Tp>
+sem_status cheb_apply_bufs(const sem_mesh* m, const Op<Tp>& op, const Tp* dinv, const Tr* r,
+                           Tr* z, int order, double lmax, const ChebCg& cg, hipStream_t s,
+                           int* applies, int kind, const ChebBufs<Tp>& b);
 
 template <typename T, typename Tp>
 sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgResult& res,
