@@ -216,6 +216,26 @@ sem_status sem_jacobi_inverse(const sem_mesh* mesh, const double* k, double h2, 
 sem_status sem_cheb_apply(const sem_mesh* mesh, const double* r, double* z, const double* k,
                           double h2, int32_t order, double lmax, sem_prec prec, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments, result and errors as sem_cheb_apply, with every work
+ * vector in one fixed library-owned device array instead of the mesh's
+ * lazily allocated work space.  No device memory is allocated or freed, and
+ * nothing is read back to the host: the call only enqueues kernels on
+ * `stream`.  The array holds 64 MiB (67108864 bytes) on every device the
+ * call runs on, from the first call for a mesh of that device until the
+ * process ends.  A call needs, with each part rounded up to 256 bytes,
+ *   prec SEM_FP64:  8 n_local + 40 n_free bytes,
+ *   otherwise:      8 n_local + 36 n_free (+ 4 n_local when k != NULL) bytes
+ * (n_local = E (N+1)^3, n_free from sem_get_info; each at least 1) and returns
+ * SEM_EINVAL, with nothing written, when that exceeds the array.  The Jacobi
+ * inverse is formed again on every call.  All calls on one device share the
+ * array: calls ordered on one stream are safe, calls that overlap in time on
+ * one device (several streams or host threads) race and give wrong results. */
+sem_status sem_cheb_apply_noalloc(const sem_mesh* mesh, const double* r, double* z,
+                                  const double* k, double h2, int32_t order, double lmax,
+                                  sem_prec prec, void* stream);
+
 /* *lmax = largest eigenvalue estimate of D^-1 A from `steps` Jacobi-CG
  * iterations (CG-Lanczos tridiagonal), started from a fixed pseudo-random
  * vector.  Blocks. */

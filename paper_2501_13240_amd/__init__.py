@@ -17,6 +17,7 @@ from .api import (
     ax,
     ax_backward,
     cheb_apply,
+    cheb_apply_noalloc,
     gll,
     gs,
     host_coarse_mesh,
@@ -45,6 +46,7 @@ __all__ = [
     "ax",
     "ax_backward",
     "cheb_apply",
+    "cheb_apply_noalloc",
     "gll",
     "gs",
     "host_coarse_mesh",

@@ -79,6 +79,8 @@ SIGNATURES = {
     "sem_jacobi_inverse": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "sem_cheb_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
                                  c_double, c_int32, c_void_p]),
+    "sem_cheb_apply_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
+                                 c_double, c_int32, c_void_p]),
     "sem_pmg_opts_default": (None, [ctypes.POINTER(PmgOpts)]),
     "sem_setup_pmg": (c_int32, [c_void_p, ctypes.POINTER(MeshDesc), ctypes.POINTER(PmgOpts),
                                 c_void_p]),

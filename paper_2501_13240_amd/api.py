@@ -239,6 +239,20 @@ def cheb_apply(mesh: Mesh, r, lmax: float, k=None, h2: float = 0.0, order: int =
     return z
 
 
+def cheb_apply_noalloc(mesh: Mesh, r, lmax: float, k=None, h2: float = 0.0, order: int = 3,
+                       prec: str = "fp64", out=None):
+    """cheb_apply through sem_cheb_apply_noalloc (work space in the library's
+    fixed device array; `out`, when given, receives z)."""
+    mesh.check_local(r, torch.float64, "r")
+    mesh.check_local(k, torch.float64, "k")
+    z = torch.empty_like(r) if out is None else out
+    mesh.check_local(z, torch.float64, "out")
+    _check(mesh._lib.sem_cheb_apply_noalloc(mesh.handle, _ptr(r), _ptr(z), _ptr(k), float(h2),
+                                            int(order), float(lmax), L.PREC[prec], _stream()),
+           "sem_cheb_apply_noalloc")
+    return z
+
+
 def pmg_apply(mesh: Mesh, r, k=None, h2: float = 0.0, prec: str = "fp32"):
     """z = V(r), one p-multigrid V-cycle (sem_pmg_apply); sets up the default
     hierarchy on first use."""

@@ -31,7 +31,7 @@ CFLAGS = [
 
 SOURCES = ["api.cpp", "host_setup.cpp", "kernels_ax.hip", "kernels_setup.hip",
            "kernels_vec.hip", "solver.hip", "pmg.hip", "pmg_host.cpp", "schwarz_host.cpp",
-           "kernels_schwarz.hip", "kernels_adv.hip", "adv_host.cpp"]
+           "kernels_schwarz.hip", "kernels_adv.hip", "adv_host.cpp", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:
