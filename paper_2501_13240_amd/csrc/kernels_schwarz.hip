@@ -47,7 +47,11 @@ __device__ __forceinline__ void fdm_tile(const T* __restrict__ src, T* __restric
   }
 }
 
-constexpr int kFdmThreads = 256;
+// wavefronts per workgroup of the one-element-per-workgroup kernel (n >= 9)
+#ifndef SEM_FDM_WAVES
+#define SEM_FDM_WAVES 4
+#endif
+constexpr int fdm_waves(int n) { return n >= 9 ? SEM_FDM_WAVES : 4; }
 
 // dst[q] = r[xmap[q]] (0 where xmap < 0) for q = t, t + NTHR, ... < P3: every
 // map entry of this thread first, then every gather, so that no gather waits
@@ -73,24 +77,24 @@ __device__ __forceinline__ void gather_box(const int32_t* __restrict__ xmap,
   }
 }
 
-template <int n, typename T>
-__global__ __launch_bounds__(kFdmThreads) void fdm_kernel(const int32_t* __restrict__ xmap,
+template <int n, typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void fdm_kernel(const int32_t* __restrict__ xmap,
                                                           const T* __restrict__ S,
                                                           const T* __restrict__ lam,
                                                           const T* __restrict__ r,
                                                           T* __restrict__ out,
                                                           const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  constexpr int P2 = n * n, P3 = P2 * n, NT = (P2 + 15) / 16, NW = kFdmThreads / 64;
+  constexpr int P2 = n * n, P3 = P2 * n, NT = (P2 + 15) / 16, NTHR = 64 * NW;
   __shared__ T sA[P3];
   __shared__ T sB[P3];
   __shared__ T sS[3][P2];
   __shared__ T sL[3][n];
   const int64_t e = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  for (int q = t; q < 3 * P2; q += kFdmThreads) (&sS[0][0])[q] = S[e * 3 * P2 + q];
-  for (int q = t; q < 3 * n; q += kFdmThreads) (&sL[0][0])[q] = lam[e * 3 * n + q];
-  gather_box<P3, kFdmThreads>(xmap + e * P3, r, sA, t);
+  for (int q = t; q < 3 * P2; q += NTHR) (&sS[0][0])[q] = S[e * 3 * P2 + q];
+  for (int q = t; q < 3 * n; q += NTHR) (&sL[0][0])[q] = lam[e * 3 * n + q];
+  gather_box<P3, NTHR>(xmap + e * P3, r, sA, t);
   __syncthreads();
   for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 0, true>(sA, sB, sS[0], tile, lane);
   __syncthreads();
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(kFdmThreads) void fdm_kernel(const int32_t* __restr
   __syncthreads();
   for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 2, true>(sA, sB, sS[2], tile, lane);
   __syncthreads();
-  for (int q = t; q < P3; q += kFdmThreads) {
+  for (int q = t; q < P3; q += NTHR) {
     const int a = q % n, b = (q / n) % n, c = q / P2;
     sB[q] = sB[q] / (sL[0][a] + sL[1][b] + sL[2][c]);
   }
@@ -109,7 +113,7 @@ __global__ __launch_bounds__(kFdmThreads) void fdm_kernel(const int32_t* __restr
   __syncthreads();
   for (int tile = wv; tile < NT; tile += NW) fdm_tile<n, T, 0, false>(sB, sA, sS[0], tile, lane);
   __syncthreads();
-  for (int q = t; q < P3; q += kFdmThreads) out[e * P3 + q] = sA[q];
+  for (int q = t; q < P3; q += NTHR) out[e * P3 + q] = sA[q];
 }
 
 // Small boxes (n <= 8, N <= 5): one wavefront per element, four elements per
@@ -173,7 +177,8 @@ hipError_t run_fdm(int64_t E, const int32_t* xmap, const T* S, const T* lam, con
     hipLaunchKernelGGL((fdm_wave_kernel<n, T>), dim3((unsigned)grid), dim3(64 * kFdmWaves), 0, s,
                        E, xmap, S, lam, r, out, skip);
   } else {
-    hipLaunchKernelGGL((fdm_kernel<n, T>), dim3((unsigned)E), dim3(kFdmThreads), 0, s, xmap, S,
+    constexpr int NW = fdm_waves(n);
+    hipLaunchKernelGGL((fdm_kernel<n, T, NW>), dim3((unsigned)E), dim3(64 * NW), 0, s, xmap, S,
                        lam, r, out, skip);
   }
   return hipGetLastError();

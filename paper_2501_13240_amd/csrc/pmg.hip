@@ -155,28 +155,26 @@ T* local_scratch(const sem_mesh* m) {
   return W.vec<T>(sizeof(T) == 8 ? W.wL : W.wL32, m->nL);
 }
 
-// Chebyshev-Schwarz kernels: the fourth-kind recurrence with S = Schwarz
-template <typename T>
-__global__ void k_schw_init(int64_t nf, const T* __restrict__ r, const T* __restrict__ q,
-                            T* __restrict__ d, T* __restrict__ rk, T* __restrict__ z, T c0,
-                            const int32_t* __restrict__ skip) {
+// The additive Schwarz sum fused with the Chebyshev recurrence: q = sum of
+// the box copies of free node g (q = S r_k), then FIRST: d = ca q, z = d;
+// else d = ca d + cb q, z += d.  q itself is never stored.
+template <typename T, bool FIRST>
+__global__ void k_schw_sum_cheb(int64_t nf, const int32_t* __restrict__ seg,
+                                const int32_t* __restrict__ perm, const T* __restrict__ box,
+                                T* __restrict__ d, T* __restrict__ z, T ca, T cb,
+                                const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   GRID_STRIDE(g, nf) {
-    const T dg = c0 * q[g];
-    d[g] = dg;
-    rk[g] = r[g];
-    z[g] = dg;
-  }
-}
-
-template <typename T>
-__global__ void k_schw_step(int64_t nf, const T* __restrict__ q, T* __restrict__ d,
-                            T* __restrict__ z, T ca, T cb, const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  GRID_STRIDE(g, nf) {
-    const T dg = ca * d[g] + cb * q[g];
-    d[g] = dg;
-    z[g] += dg;
+    const T q = segment_sum<T>(perm, box, seg[g], seg[g + 1]);
+    if constexpr (FIRST) {
+      const T dg = ca * q;
+      d[g] = dg;
+      z[g] = dg;
+    } else {
+      const T dg = ca * d[g] + cb * q;
+      d[g] = dg;
+      z[g] += dg;
+    }
   }
 }
 
@@ -200,7 +198,9 @@ sem_status schwarz_apply(const PmgLevel& L, const T* r, T* z, const int32_t* ski
   return SEM_OK;
 }
 
-// z = p_m(S A) S r with the fourth-kind coefficients (as the Jacobi version)
+// z = p_m(S A) S r with the fourth-kind coefficients (as the Jacobi version).
+// Each Schwarz sum carries the recurrence's d and z update (k_schw_sum_cheb),
+// and the first residual r_1 = r - A d_0 is formed from r directly.
 template <typename T>
 sem_status cheb_schwarz(Pmg& P, PmgLevel& L, const T* r, T* z, const CgScalars* outer,
                         hipStream_t s, int* applies) {
@@ -210,26 +210,33 @@ sem_status cheb_schwarz(Pmg& P, PmgLevel& L, const T* r, T* z, const CgScalars* 
   const int32_t* skip = outer ? &outer->done : nullptr;
   T* d = P.vec<T>(L, 5);
   T* rk = P.vec<T>(L, 6);
-  T* q = P.vec<T>(L, 7);
   T* wL = local_scratch<T>(m);
-  if (!d || !rk || !q || !wL) return fail(SEM_ENOMEM, "multigrid work space");
+  T* box = box_of<T>(L.sch);
+  if (!d || !rk || !wL) return fail(SEM_ENOMEM, "multigrid work space");
+  if (!box) return fail(SEM_EINVAL, "Schwarz factors missing");
   Op<T> op = op_of<T>(L);
   op.skip = skip;
   const double lmax = L.rho_hat;
+  const int32_t* xseg = L.sch.xseg.as<int32_t>();
+  const int32_t* xperm = L.sch.xperm.as<int32_t>();
   sem_status st;
-  if ((st = schwarz_apply<T>(L, r, q, skip, s))) return st;
-  hipLaunchKernelGGL((k_schw_init<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf, r, q, d, rk,
-                     z, (T)(4.0 / (3.0 * lmax)), skip);
+  SEM_HIP(launch_fdm<T>(L.sch, m->E, r, box, skip, s));
+  hipLaunchKernelGGL((k_schw_sum_cheb<T, true>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
+                     xseg, xperm, box, d, z, (T)(4.0 / (3.0 * lmax)), T(0), skip);
   for (int k = 1; k < P.smooth_order; ++k) {
     if ((st = apply_op<T>(m, W, op, d, wL, s, false))) return st;
     if (applies) ++*applies;
-    hipLaunchKernelGGL((k_seg_dec<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
-                       m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, skip);
-    if ((st = schwarz_apply<T>(L, rk, q, skip, s))) return st;
+    if (k == 1)
+      hipLaunchKernelGGL((k_seg_sub<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
+                         m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, r, rk, skip);
+    else
+      hipLaunchKernelGGL((k_seg_dec<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
+                         m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, skip);
+    SEM_HIP(launch_fdm<T>(L.sch, m->E, rk, box, skip, s));
     const double ca = (2.0 * k - 1.0) / (2.0 * k + 3.0);
     const double cb = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
-    hipLaunchKernelGGL((k_schw_step<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf, q, d, z,
-                       (T)ca, (T)cb, skip);
+    hipLaunchKernelGGL((k_schw_sum_cheb<T, false>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
+                       xseg, xperm, box, d, z, (T)ca, (T)cb, skip);
   }
   SEM_CHECK_LAUNCH("Chebyshev-Schwarz");
   return SEM_OK;
