@@ -8,6 +8,8 @@
 // free node completes z = sum_e R_e^T A~_e^{-1} R_e r.  Each 1-D transform of
 // the box is a batch of 16-column tiles C = M X on the matrix cores (16x16x4
 // MFMA in FP64 or FP32) with M = S or S^T of this element, read from LDS.
+#include <algorithm>
+
 #include "mfma_16x16x4.hpp"
 #include "schwarz.hpp"
 
@@ -47,11 +49,59 @@ __device__ __forceinline__ void fdm_tile(const T* __restrict__ src, T* __restric
   }
 }
 
+// The same tile with this lane's fragments of M (one per k-step) already in
+// registers: a transform loads them once for all of its tiles.
+template <int n, typename T>
+__device__ __forceinline__ void fdm_frag(const T* __restrict__ S, bool trans, int lane,
+                                         T (&af)[(n + 3) / 4]) {
+  constexpr int KS = (n + 3) / 4;
+  const int kk = lane >> 4, mrow = lane & 15;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int l = 4 * s + kk;
+    af[s] = (mrow < n && l < n) ? (trans ? S[l * n + mrow] : S[mrow * n + l]) : T(0);
+  }
+}
+
+template <int n, typename T, int DIR>
+__device__ __forceinline__ void fdm_tile_f(const T* __restrict__ src, T* __restrict__ dst,
+                                           const T (&af)[(n + 3) / 4], int tile, int lane) {
+  constexpr int P2 = n * n, KS = (n + 3) / 4;
+  const int col = tile * 16 + (lane & 15);
+  const int kk = lane >> 4;
+  const bool cval = col < P2;
+  const int c1 = cval ? col / n : 0, c0 = cval ? col % n : 0;
+  typename Mm<T>::V acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int l = 4 * s + kk;
+    T b = T(0);
+    if (cval && l < n) {
+      const int ad = DIR == 0 ? c1 * P2 + c0 * n + l : DIR == 1 ? c1 * P2 + l * n + c0 : l * P2 + col;
+      b = src[ad];
+    }
+    acc = Mm<T>::mma(af[s], b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = Mm<T>::row(lane, r);
+    if (cval && row < n) {
+      const int ad =
+          DIR == 0 ? c1 * P2 + c0 * n + row : DIR == 1 ? c1 * P2 + row * n + c0 : row * P2 + col;
+      dst[ad] = acc[r];
+    }
+  }
+}
+
 // wavefronts per workgroup of the one-element-per-workgroup kernel (n >= 9)
 #ifndef SEM_FDM_WAVES
 #define SEM_FDM_WAVES 4
 #endif
 constexpr int fdm_waves(int n) { return n >= 9 ? SEM_FDM_WAVES : 4; }
+// persistent, software-pipelined local solves for n >= 9 (see fdm_pipe_kernel)
+#ifndef SEM_FDM_PIPE
+#define SEM_FDM_PIPE 1
+#endif
 
 // dst[q] = r[xmap[q]] (0 where xmap < 0) for q = t, t + NTHR, ... < P3: every
 // map entry of this thread first, then every gather, so that no gather waits
@@ -116,6 +166,100 @@ __global__ __launch_bounds__(64 * NW) void fdm_kernel(const int32_t* __restrict_
   for (int q = t; q < P3; q += NTHR) out[e * P3 + q] = sA[q];
 }
 
+// The same with a persistent grid: each workgroup walks the elements
+// e = blockIdx.x, blockIdx.x + gridDim.x, ... and keeps the next element's
+// loads in flight while it transforms the current one (subdomain-map loads
+// during the first transform, then the residual gathers and the S and lam
+// factors during the other five), so the gather latency no longer separates
+// the transform phases of one workgroup.
+template <int n, typename T, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 ? 8 : 1))) void fdm_pipe_kernel(int64_t E,
+                                                           const int32_t* __restrict__ xmap,
+                                                           const T* __restrict__ S,
+                                                           const T* __restrict__ lam,
+                                                           const T* __restrict__ r,
+                                                           T* __restrict__ out,
+                                                           const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int P2 = n * n, P3 = P2 * n, NT = (P2 + 15) / 16, NTHR = 64 * NW;
+  constexpr int NF = 3 * P2 + 3 * n;                  // S then lam of one element
+  constexpr int PPT = (P3 + NTHR - 1) / NTHR, FPT = (NF + NTHR - 1) / NTHR;
+  __shared__ T sA[P3];
+  __shared__ T sB[P3];
+  __shared__ T sF[NF];
+  const T* sS0 = sF;
+  const T* sS1 = sF + P2;
+  const T* sS2 = sF + 2 * P2;
+  const T* sL = sF + 3 * P2;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int32_t gi[PPT];
+  T rv[PPT], fv[FPT];
+  T af[(n + 3) / 4];
+  auto load_map = [&](int64_t e) {
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int q = t + s * NTHR;
+      gi[s] = q < P3 ? xmap[e * P3 + q] : -1;
+    }
+  };
+  auto load_vals = [&](int64_t e) {
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) rv[s] = gi[s] >= 0 ? r[gi[s]] : T(0);
+#pragma unroll
+    for (int s = 0; s < FPT; ++s) {
+      const int f = t + s * NTHR;
+      fv[s] = f < 3 * P2 ? S[e * 3 * P2 + f] : f < NF ? lam[e * 3 * n + (f - 3 * P2)] : T(0);
+    }
+  };
+  int64_t e = blockIdx.x;
+  if (e >= E) return;  // uniform over the workgroup
+  load_map(e);
+  load_vals(e);
+  for (; e < E; e += gridDim.x) {
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int q = t + s * NTHR;
+      if (q < P3) sA[q] = rv[s];
+    }
+#pragma unroll
+    for (int s = 0; s < FPT; ++s) {
+      const int f = t + s * NTHR;
+      if (f < NF) sF[f] = fv[s];
+    }
+    __syncthreads();
+    const int64_t en = e + gridDim.x;
+    const bool more = en < E;
+    if (more) load_map(en);
+    fdm_frag<n, T>(sS0, true, lane, af);
+    for (int tile = wv; tile < NT; tile += NW) fdm_tile_f<n, T, 0>(sA, sB, af, tile, lane);
+    __syncthreads();
+    if (more) load_vals(en);
+    fdm_frag<n, T>(sS1, true, lane, af);
+    for (int tile = wv; tile < NT; tile += NW) fdm_tile_f<n, T, 1>(sB, sA, af, tile, lane);
+    __syncthreads();
+    fdm_frag<n, T>(sS2, true, lane, af);
+    for (int tile = wv; tile < NT; tile += NW) fdm_tile_f<n, T, 2>(sA, sB, af, tile, lane);
+    __syncthreads();
+    for (int q = t; q < P3; q += NTHR) {
+      const int a = q % n, b = (q / n) % n, c = q / P2;
+      sB[q] = sB[q] / (sL[a] + sL[n + b] + sL[2 * n + c]);
+    }
+    __syncthreads();
+    fdm_frag<n, T>(sS2, false, lane, af);
+    for (int tile = wv; tile < NT; tile += NW) fdm_tile_f<n, T, 2>(sB, sA, af, tile, lane);
+    __syncthreads();
+    fdm_frag<n, T>(sS1, false, lane, af);
+    for (int tile = wv; tile < NT; tile += NW) fdm_tile_f<n, T, 1>(sA, sB, af, tile, lane);
+    __syncthreads();
+    fdm_frag<n, T>(sS0, false, lane, af);
+    for (int tile = wv; tile < NT; tile += NW) fdm_tile_f<n, T, 0>(sB, sA, af, tile, lane);
+    __syncthreads();
+    for (int q = t; q < P3; q += NTHR) out[e * P3 + q] = sA[q];
+    __syncthreads();  // sA and sF are restaged for the next element
+  }
+}
+
 // Small boxes (n <= 8, N <= 5): one wavefront per element, four elements per
 // workgroup.  A wavefront's LDS operations complete in program order, so the
 // six transforms need no workgroup barrier; a wavefront-scope fence between
@@ -178,8 +322,25 @@ hipError_t run_fdm(int64_t E, const int32_t* xmap, const T* S, const T* lam, con
                        E, xmap, S, lam, r, out, skip);
   } else {
     constexpr int NW = fdm_waves(n);
+#if SEM_FDM_PIPE
+    // persistent grid: the resident workgroups of the device, at most one per element
+    static int resident = 0;
+    if (resident == 0) {
+      int dev = 0, cus = 0, per_cu = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fdm_pipe_kernel<n, T, NW>,
+                                                       64 * NW, 0) != hipSuccess)
+        return hipErrorUnknown;
+      resident = std::max(1, cus * per_cu);
+    }
+    const int64_t grid = std::min<int64_t>(E, resident);
+    hipLaunchKernelGGL((fdm_pipe_kernel<n, T, NW>), dim3((unsigned)grid), dim3(64 * NW), 0, s, E,
+                       xmap, S, lam, r, out, skip);
+#else
     hipLaunchKernelGGL((fdm_kernel<n, T, NW>), dim3((unsigned)E), dim3(64 * NW), 0, s, xmap, S,
                        lam, r, out, skip);
+#endif
   }
   return hipGetLastError();
 }
