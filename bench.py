@@ -261,12 +261,84 @@ def mixed_vs_fp64(sem, only=""):
     out["fastest_mixed"] = best
     if best and "fp64_jacobi_cg" in out:
         out["speedup_vs_fp64"] = out["fp64_jacobi_cg"]["ms"] / out[best]["ms"]
+    if "fp64_cg_fp32_pmg" in out:
+        # whole-iteration roofline of the FP32-cycle p-multigrid solve
+        total, parts = pmg_cube_iteration_bytes()
+        v = out["fp64_cg_fp32_pmg"]
+        ms_it = v["ms"] / v["iters"]
+        out["pmg_roofline"] = {
+            "variant": "fp64_cg_fp32_pmg", "bound": "hbm",
+            "ms_per_iteration": ms_it,
+            "algorithmic_bytes_per_iteration": total,
+            "achieved": total / (ms_it * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": total / (ms_it * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "timing": "solve time / iterations (the first V-cycle, z_0 = M r_0, included)",
+            "bytes_by_kernel": parts,
+        }
     if "fp64_pmg_fcg" in out and "fp64_cg_fp32_pmg" in out:
         # the same preconditioner in FP64 and with the FP32 cycle
         out["pmg_fp32_cycle_speedup_vs_fp64_pmg"] = (out["fp64_pmg_fcg"]["ms"]
                                                      / out["fp64_cg_fp32_pmg"]["ms"])
     M.close()
     return out
+
+
+def pmg_cube_iteration_bytes(nel=32, orders=(9, 4, 2, 1), smooth_order=4, coarse_iters=30):
+    """Algorithmic HBM bytes of one iteration of FP64 flexible CG preconditioned
+    by one FP32 Schwarz-smoothed V-cycle on the all-Neumann nel^3 cube (every
+    kernel the iteration launches, each array counted once per access; index
+    arrays 4 B, FP32 values 4 B, FP64 values 8 B).  Returns (total, per-kernel
+    dict of bytes per iteration).  Counts of the structured mesh:
+    local points E (N+1)^3, free nodes (nel N + 1)^3, single-copy nodes the
+    element interiors and the boundary-face interiors, box copies E ((N+1)^3 +
+    6 (N+1)^2) minus the (N+1)^2 layer missing behind each boundary face."""
+    E = nel ** 3
+    faces_b = 6 * nel * nel
+
+    def sizes(N):
+        nL = E * (N + 1) ** 3
+        nf = (nel * N + 1) ** 3
+        n1 = E * (N - 1) ** 3 + faces_b * (N - 1) ** 2
+        box_pts = (N + 3) ** 3
+        box_copies = E * ((N + 1) ** 3 + 6 * (N + 1) ** 2) - faces_b * (N + 1) ** 2
+        return nL, nf, n1, box_pts, box_copies
+
+    out = {}
+
+    def add(name, b):
+        out[name] = out.get(name, 0.0) + b
+
+    # outer FP64 flexible CG
+    nL, nf, n1, _, _ = sizes(orders[0])
+    add("ax FP64 in-solve (64 B per local point)", 64.0 * nL)
+    add("shared-node sum (12 B per shared copy, 20 B per shared node)",
+        12.0 * (nL - n1) + 20.0 * (nf - n1))
+    add("CG update (48 B per free node)", 48.0 * nf)
+    add("residual to FP32 (12 B per free node)", 12.0 * nf)
+    add("z and dots (28 B per free node)", 28.0 * nf)
+    add("p update (24 B per free node)", 24.0 * nf)
+    # V-cycle (FP32)
+    for lev, N in enumerate(orders):
+        nL, nf, n1, bp, bc = sizes(N)
+        if lev == len(orders) - 1:
+            # coarsest: fixed Jacobi-PCG iterations (operator 32 B per local point,
+            # sum 8 B per copy + 12 per node, update 20 B and p update 16 B per node)
+            add("coarse CG", coarse_iters * (32.0 * nL + 8.0 * nL + 12.0 * nf + 36.0 * nf))
+            break
+        m = smooth_order
+        add("ax FP32 (32 B per local point)", (2 * (m - 1) + 2) * 32.0 * nL)
+        add("Schwarz local solves (12 B per box point + factors)",
+            2 * m * E * (12.0 * bp + 4.0 * (3 * (N + 3) ** 2 + 3 * (N + 3))))
+        add("Schwarz sums with the recurrence (8 B per box copy + 12 / 20 B per node)",
+            2 * (8.0 * bc + 12.0 * nf) + 2 * (m - 1) * (8.0 * bc + 20.0 * nf))
+        add("residual sums (8 B per local copy + 12 B per node)", (2 * (m - 1) + 2) * (8.0 * nL + 12.0 * nf))
+        nLc, nfc = sizes(orders[lev + 1])[:2]
+        add("restriction (16 B per fine point + 4 per coarse point, then 8 B per coarse copy + 8 per coarse node)",
+            16.0 * nL + 4.0 * nLc + 8.0 * nLc + 8.0 * nfc)
+        add("prolongation (8 B per coarse point + 4 per fine point, then 8 B per copy + 12 per node)",
+            8.0 * nLc + 4.0 * nL + 8.0 * nL + 12.0 * nf)
+        add("post-smoothing add (12 B per node)", 12.0 * nf)
+    return sum(out.values()), out
 
 
 def pmg_setup(sem, M, b, name):
