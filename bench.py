@@ -387,7 +387,10 @@ def to_tolerance(sem, M, b, b_host):
 
 def gs_rate(sem, M, reps):
     """sem_gs on the benchmark mesh: 20 B per local copy of a shared node
-    (index 4, read 8, write 8) + 4 B per shared node (segment offset)."""
+    (index 4, read 8, write 8) + 4 B per shared node (segment offset).
+    sector_floor_bytes: what any gather-scatter on the [E][P] FP64 layout must
+    move, since memory is read and written in 32-byte sectors: every sector that
+    holds a shared copy, read and written once, plus the index arrays."""
     import torch
 
     mult = M.multiplicity()
@@ -395,6 +398,8 @@ def gs_rate(sem, M, reps):
     copies = int(shared.sum())
     nodes = float((1.0 / mult[shared]).sum())
     alg = 20.0 * copies + 4.0 * nodes
+    sectors = int(shared.reshape(-1, 4).any(dim=1).sum())
+    floor = 2.0 * 32.0 * sectors + 4.0 * copies + 4.0 * nodes
     v = torch.randn(M.E, M.P, dtype=torch.float64, device="cuda")
     for _ in range(3):
         sem.gs(M, v)
@@ -406,7 +411,9 @@ def gs_rate(sem, M, reps):
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) / reps * 1e3
     return {"us": us, "algorithmic_bytes": alg, "gb_s": alg / us / 1e3,
-            "shared_copies": copies}
+            "shared_copies": copies, "sector_floor_bytes": floor,
+            "sector_floor_gb_s": floor / us / 1e3,
+            "sector_floor_frac": floor / us / 1e3 / PEAK_HBM_GBS}
 
 
 def advection_rate(sem, M, m, reps):
