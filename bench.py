@@ -333,10 +333,12 @@ def pmg_cube_iteration_bytes(nel=32, orders=(9, 4, 2, 1), smooth_order=4, coarse
             2 * (8.0 * bc + 12.0 * nf) + 2 * (m - 1) * (8.0 * bc + 20.0 * nf))
         add("residual sums (8 B per local copy + 12 B per node)", (2 * (m - 1) + 2) * (8.0 * nL + 12.0 * nf))
         nLc, nfc = sizes(orders[lev + 1])[:2]
-        add("restriction (16 B per fine point + 4 per coarse point, then 8 B per coarse copy + 8 per coarse node)",
-            16.0 * nL + 4.0 * nLc + 8.0 * nLc + 8.0 * nfc)
-        add("prolongation (8 B per coarse point + 4 per fine point, then 8 B per copy + 12 per node)",
-            8.0 * nLc + 4.0 * nL + 8.0 * nL + 12.0 * nf)
+        add("restriction (4 B per fine point, 8 per fine node, 4 per coarse point; then 8 B "
+            "per coarse copy + 8 per coarse node)",
+            4.0 * nL + 8.0 * nf + 4.0 * nLc + 8.0 * nLc + 8.0 * nfc)
+        add("prolongation (4 B per coarse point and node, 4 per fine point; then 8 B per "
+            "copy + 12 per node)",
+            4.0 * nLc + 4.0 * nfc + 4.0 * nL + 8.0 * nL + 12.0 * nf)
         add("post-smoothing add (12 B per node)", 12.0 * nf)
     return sum(out.values()), out
 

@@ -472,6 +472,38 @@ def test_pcg_first_kind_chebyshev_matches_oracle(precond_prec):
     assert rel(xf, jac["x"]) <= 1e-8
 
 
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("cfg", [2, 5])  # Dirichlet plates, periodic sides / all Neumann
+def test_chebyshev_inside_cg_fixed_iterations_match_oracle(cfg, order, store_form):
+    """From N = 5 a Chebyshev preconditioner runs inside the flexible CG's own
+    kernels on the split operator (the first vector in the update, one step
+    kernel per operator apply, z in the preconditioner's precision).  In FP64
+    the first 30 iterations must follow the oracle's flexible CG with the same
+    Chebyshev polynomial (residual history and x_30 to 1e-8), for one step
+    (order 2), a first and a last step (3) and a middle step (4).  The FP32
+    preconditioner is held to the FP64 oracle's history within 5e-3."""
+    m, fld = config_mesh(cfg, N=7, shape=(4, 4, 3))
+    M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N)
+    b_or = P.project(P.num.from_local_consistent(fld["b"]))
+    lmax = 1.1 * sem.lmax_estimate(M)
+    ref = P.solve(b_or, rtol=1e-30, max_iter=30, precond="chebyshev", m=order, rho_hat=lmax,
+                  fixed_iters=True)
+    x, st = sem.solve(M, dev(fld["b"]), precond="chebyshev", precond_prec="fp64",
+                      cheb_order=order, lmax=lmax, max_iter=30, fixed_iters=True, history=True)
+    assert st["iters"] == 30
+    np.testing.assert_allclose(st["history"], ref["res_hist"], rtol=1e-8)
+    xf = P.num.from_local_consistent(x.cpu().numpy())
+    assert rel(xf, ref["x"]) <= 1e-8
+    if order == 3:
+        x32, st32 = sem.solve(M, dev(fld["b"]), precond="chebyshev", precond_prec="fp32",
+                              cheb_order=order, lmax=lmax, max_iter=30, fixed_iters=True,
+                              history=True)
+        d = np.max(np.abs(np.asarray(st32["history"]) / ref["res_hist"] - 1.0))
+        print(f"cfg {cfg}: FP32 Chebyshev history vs FP64 oracle, max rel diff {d:.2e}")
+        assert d <= 5e-3
+
+
 @pytest.mark.parametrize("identify_interior", [False, True])
 def test_pcg_split_and_gather_paths_match_oracle(identify_interior, store_form):
     # From N = 5 the in-solve operator writes single-copy nodes straight to the
