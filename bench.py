@@ -418,6 +418,25 @@ def gs_rate(sem, M, reps):
             "sector_floor_frac": floor / us / 1e3 / PEAK_HBM_GBS}
 
 
+PEAK_MFMA_TFLOPS = {8: 78.6, 4: 157.3}  # MI355X dense matrix cores, FP64 / FP32
+
+
+def dealias_mfma_per_element(N, nf):
+    """16x16x4 MFMA products the dealiased convective-term kernel executes per
+    element: per velocity component the three interpolation stages, per field
+    the derivative stages (2 i-, 3 j- and 3 k-stage products) and the three
+    projection stages; each stage is ceil(columns / 16) tiles of ceil(K / 4)
+    products (padded rows and columns included)."""
+    n, M = N + 1, (3 * (N + 1)) // 2
+    nt = lambda c: (c + 15) // 16
+    kn, km = (n + 3) // 4, (M + 3) // 4
+    i0, i1, i2 = nt(n * n), nt(n * M), nt(M * M)
+    u_pass = (i0 + i1 + i2) * kn
+    f_pass = (2 * i0 + 3 * i1 + 3 * i2) * kn
+    back = (nt(M * M) + nt(n * M) + nt(n * n)) * km
+    return 3 * u_pass + nf * (f_pass + back)
+
+
 def advection_rate(sem, M, m, reps):
     """sem_advect on the benchmark mesh (smooth seeded velocity and scalar),
     and sem_advect_fields on the four fields of a Boussinesq step (the scalar
@@ -466,6 +485,11 @@ def advection_rate(sem, M, m, reps):
                             "hbm_frac": alg / ms / 1e6 / PEAK_HBM_GBS,
                             "glocal_points_s": nf * M.E * M.P / (ms * 1e-3) / 1e9,
                             "setup_s": setup_s}
+                if rule == "dealias":
+                    # the matrix-core side of the same launch (executed products)
+                    fl = 2048.0 * dealias_mfma_per_element(M.N, nf) * M.E
+                    out[key]["mfma_tflops"] = fl / (ms * 1e-3) / 1e12
+                    out[key]["mfma_frac"] = fl / (ms * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[width]
                 log(f"  advect {key}: {ms * 1e3:.1f} us, {out[key]['gb_s']:.0f} GB/s")
     return out
 

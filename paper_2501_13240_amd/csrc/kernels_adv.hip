@@ -18,7 +18,9 @@
 // most of the HBM traffic.  With one field the kernel reaches about half of
 // the HBM peak: the factors of a pass can be requested only one pass ahead
 // within the register budget, less than the loaded latency.  With several
-// fields sharing V, it is bound by the matrix cores.
+// fields sharing V most of the work is MFMA products and LDS stages, at about
+// a third of the matrix cores' peak (the stages' barrier and LDS latencies,
+// at two workgroups per CU).
 //
 // Collocation (the GLL nodes themselves): one thread per node, derivative
 // sums over LDS.
