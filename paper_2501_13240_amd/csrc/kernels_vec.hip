@@ -4,6 +4,8 @@
 // sorted-index segmented sums: every global node owns a contiguous segment
 // of a permutation listing its local copies in ascending order, so one thread
 // per node sums its copies in a fixed order (bit-reproducible, no atomics).
+#include <climits>
+
 #include "common.hpp"
 
 namespace sem {
@@ -20,15 +22,20 @@ inline unsigned grid_for(int64_t n, int64_t cap = 65536) {
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (n); \
        idx += (int64_t)gridDim.x * blockDim.x)
 
-// v <- Q Q^T v on local copies of shared nodes (single-copy nodes are fixed points)
+// v <- Q Q^T v on local copies of shared nodes (single-copy nodes are fixed points).
+// Workgroups in the XCD-contiguous order (xcd_order): the copies of
+// neighbouring nodes, which share 32-byte sectors, are read and written
+// through one L2.
 template <typename T>
-__global__ void gs_local_kernel(int64_t ns, const int32_t* __restrict__ seg,
-                                const int32_t* __restrict__ perm, T* __restrict__ v) {
-  GRID_STRIDE(g, ns) {
-    const int32_t a = seg[g], b = seg[g + 1];
-    const T s = segment_sum<T>(perm, v, a, b);
-    for (int32_t p = a; p < b; ++p) v[perm[p]] = s;
-  }
+__global__ __launch_bounds__(kVecBlock) void gs_local_kernel(int64_t ns,
+                                                             const int32_t* __restrict__ seg,
+                                                             const int32_t* __restrict__ perm,
+                                                             T* __restrict__ v) {
+  const int64_t g = xcd_order(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (g >= ns) return;
+  const int32_t a = seg[g], c = seg[g + 1];
+  const T s = segment_sum<T>(perm, v, a, c);
+  for (int32_t p = a; p < c; ++p) v[perm[p]] = s;
 }
 
 template <typename T>
@@ -114,7 +121,10 @@ __global__ void pseudo_random_kernel(double* __restrict__ v, int64_t n, uint64_t
 template <typename T>
 hipError_t launch_gs_local(const sem_mesh* m, T* v, hipStream_t s) {
   if (m->n_shared == 0) return hipSuccess;
-  hipLaunchKernelGGL((gs_local_kernel<T>), dim3(grid_for(m->n_shared)), dim3(kVecBlock), 0, s,
+  // one node per thread (the grid covers every node; no grid-stride loop)
+  const int64_t blocks = (m->n_shared + kVecBlock - 1) / kVecBlock;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gs_local_kernel<T>), dim3((unsigned)blocks), dim3(kVecBlock), 0, s,
                      m->n_shared, m->gseg.as<int32_t>(), m->gperm.as<int32_t>(), v);
   return hipGetLastError();
 }
