@@ -238,7 +238,7 @@ sem_status sem_cheb_apply_noalloc(const sem_mesh* mesh, const double* r, double*
 
 /* *lmax = largest eigenvalue estimate of D^-1 A from `steps` Jacobi-CG
  * iterations (CG-Lanczos tridiagonal), started from a fixed pseudo-random
- * vector.  Blocks. */
+ * vector.  Blocks.  SEM_EINVAL for a mesh with no free node. */
 sem_status sem_lmax_estimate(const sem_mesh* mesh, const double* k, double h2, int32_t steps,
                              double* lmax, void* stream);
 
@@ -250,7 +250,8 @@ sem_status sem_lmax_estimate(const sem_mesh* mesh, const double* k, double h2, i
  * h2 = 0 the constant mode is removed from b and from x (zero mean over the
  * unique nodes).  k: DEVICE double [E][P] or NULL.  Blocks the host (it reads
  * residual norms).  stats may be NULL.  Returns SEM_ENOCONV / SEM_EBREAKDOWN
- * with x = last iterate and stats filled. */
+ * with x = last iterate and stats filled.  A mesh with no free node (every
+ * node Dirichlet) returns SEM_OK at once with x = 0 and 0 iterations. */
 sem_status sem_pcg_solve(const sem_mesh* mesh, const double* b, double* x, const double* k,
                          double h2, const sem_solve_opts* opts, sem_solve_stats* stats,
                          void* stream);
@@ -343,7 +344,8 @@ sem_status sem_pmg_info(const sem_mesh* mesh, int32_t* n_levels, int32_t* orders
 /* z = V(r): one V-cycle for A(k) (+ h2 B).  r, z: DEVICE double [E][P]
  * copy-consistent (values at Dirichlet copies ignored / returned 0); k DEVICE
  * double [E][P] or NULL.  prec: SEM_FP64 or SEM_FP32 (arithmetic of the
- * cycle).  Blocks on the first call for given k, h2 (level bounds). */
+ * cycle).  Blocks on the first call for given k, h2 (level bounds).  With no
+ * free node z = 0. */
 sem_status sem_pmg_apply(const sem_mesh* mesh, const double* r, double* z, const double* k,
                          double h2, sem_prec prec, void* stream);
 

@@ -391,6 +391,19 @@ static sem_status solve_free(const sem_mesh* m, const double* k, double h2,
   sem_status st = W.init(m, std::max(opts.max_iter, 1));
   if (st) return st;
   W.ev_used = 0;
+  if (m->n_free == 0) {
+    // no unknowns (every node Dirichlet): the solution is empty, so the
+    // output holds 0 at every copy; no preconditioner is set up
+    double* xf = W.vec<double>(W.x, 1);
+    if (!xf) return fail(SEM_ENOMEM, "work space");
+    if ((st = store(xf))) return st;
+    SEM_HIP(hipStreamSynchronize(s));
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->converged = 1;
+    }
+    return SEM_OK;
+  }
   hipEvent_t t0, t1;
   SEM_HIP(hipEventCreate(&t0));
   SEM_HIP(hipEventCreate(&t1));
@@ -1051,6 +1064,10 @@ sem_status sem_pmg_apply(const sem_mesh* m, const double* r, double* z, const do
   if (!m->pmg) return fail(SEM_EINVAL, "no multigrid hierarchy: call sem_setup_pmg first");
   hipStream_t s = (hipStream_t)stream;
   sem_status st;
+  if (m->n_free == 0) {  // no unknowns: z = 0 at every copy
+    SEM_HIP(launch_fill<double>(z, m->nL, 0.0, s));
+    return SEM_OK;
+  }
   if ((st = pmg_prepare(m, k, h2, prec == SEM_FP64, s))) return st;
   SolveWork& W = work_of(m);
   double* rf = W.vec<double>(W.tmpf, m->n_free);
@@ -1205,6 +1222,7 @@ sem_status sem_lmax_estimate(const sem_mesh* m, const double* k, double h2, int3
   if (!lmax) return fail(SEM_EINVAL, "lmax must not be NULL");
   if (steps < 1) return fail(SEM_EINVAL, "steps must be >= 1");
   if (!(h2 >= 0.0) || !std::isfinite(h2)) return fail(SEM_EINVAL, "h2 must be finite and >= 0");
+  if (m->n_free == 0) return fail(SEM_EINVAL, "the mesh has no free node (every node Dirichlet)");
   return estimate_lmax(m, work_of(m), k, h2, steps, lmax, (hipStream_t)stream);
 }
 
