@@ -383,6 +383,18 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
       lvq[s] = ld_stream(lmap + e * P + (qr < P ? qr : P - 1));
     }
   }
+  // the geometric factors (and k) are requested before the first routing
+  // code is used, so the bulk of the stream does not wait for the codes
+#pragma unroll
+  for (int s = 0; s < PPT; ++s) {
+    const int qr = t + s * TPB;
+    const int q = qr < P ? qr : P - 1;
+    const int64_t idx = e * P + q;
+    const T* g = G + e * 6 * P + q;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gq[s][c] = ld_stream(g + c * P);
+    kq[s] = use_k ? ld_stream(kf + idx) : T(1);
+  }
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
     const int qr = t + s * TPB;
@@ -398,10 +410,6 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
     } else {
       uq[s] = ld_stream(u + idx);
     }
-    const T* g = G + e * 6 * P + q;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) gq[s][c] = ld_stream(g + c * P);
-    kq[s] = use_k ? ld_stream(kf + idx) : T(1);
   }
   // derivative-matrix fragments: forward A = D, transposed A = D^T
   T af[KS], at[KS];
