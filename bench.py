@@ -164,6 +164,12 @@ def oracle_errors(out):
                                             / np.linalg.norm(adj_b))
         r["kbar_rel_diff_vs_oracle"] = rel(g["kbar"], kb)
         r["kbar_autograd_rel_diff_vs_oracle"] = rel(g["kbar_autograd"], kb)
+        if "pmg_fp32" in r:
+            xpf = P.num.from_local_consistent(g["x_pmg"])
+            r["pmg_fp32"]["oracle_rel_res_forward"] = float(np.linalg.norm(b - P.apply(xpf))
+                                                            / np.linalg.norm(b))
+            # against the oracle's gradient at the Jacobi-CG solutions (both at 1e-12)
+            r["pmg_fp32"]["kbar_rel_diff_vs_oracle"] = rel(g["kbar_pmg"], kb)
         log(f"  gradient: forward res {r['oracle_rel_res_forward']:.2e}, adjoint res "
             f"{r['oracle_rel_res_adjoint']:.2e}, kbar {r['kbar_rel_diff_vs_oracle']:.2e}")
 
@@ -552,19 +558,35 @@ def gradient_timing(sem):
     w = torch.where(sem.mask(M, torch.ones_like(f)) > 0, 1.0 / free, torch.zeros_like(f))
     k0 = torch.tensor(fld["k"], device="cuda")
     out = {}
-    for rep in range(2):
+
+    def timed_pass(opts):
         k = k0.clone().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x = sem.sem_solve(M, b, k=k, h2=fld["h2"], rtol=1e-12)
+        x = sem.sem_solve(M, b, k=k, h2=fld["h2"], rtol=1e-12, **opts)
         loss = torch.sum(w * (x - target) ** 2)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out = {"forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
-               "n_unique": M.info["n_unique"]}
+        return x, k, (t1 - t0) * 1e3, (t2 - t1) * 1e3
+
+    for rep in range(2):
+        x, k, fwd, bwd = timed_pass({})
+        out = {"forward_ms": fwd, "backward_ms": bwd, "n_unique": M.info["n_unique"]}
+    # the same forward and backward with FP64 flexible CG preconditioned by the
+    # FP32 p-multigrid cycle (k interpolated to every level); the hierarchy is
+    # built and the level bounds formed outside the timing
+    M.setup_pmg()
+    pmg = dict(precond="pmg", precond_prec="fp32")
+    for rep in range(2):
+        xp, kp, fwd, bwd = timed_pass(pmg)
+    out["pmg_fp32"] = {"forward_ms": fwd, "backward_ms": bwd,
+                       "x_rel_diff_vs_jacobi": float(torch.linalg.norm(xp.detach() - x.detach())
+                                                     / torch.linalg.norm(x.detach())),
+                       "kbar_rel_diff_vs_jacobi": float(torch.linalg.norm(kp.grad - k.grad)
+                                                        / torch.linalg.norm(k.grad))}
     # for the oracle's checks (untimed): the cotangent autograd passes,
     # dL/dx = 2 w (x - target), and the adjoint solution lam = bbar x copies
     xd = x.detach()
@@ -573,7 +595,9 @@ def gradient_timing(sem):
                                        max_iter=20000)
     GRAD_CHECK.update(x=xd.cpu().numpy(), xbar=xbar.cpu().numpy(),
                       lam=(bbar * free).cpu().numpy(), kbar=kbar.cpu().numpy(),
-                      kbar_autograd=k.grad.detach().cpu().numpy(), result=out)
+                      kbar_autograd=k.grad.detach().cpu().numpy(), result=out,
+                      x_pmg=xp.detach().cpu().numpy(),
+                      kbar_pmg=kp.grad.detach().cpu().numpy())
     M.close()
     return out
 

@@ -40,11 +40,18 @@ def _loss(M, x, target):
     return torch.sum(d * d / M.multiplicity())
 
 
-def test_autograd_matches_oracle_adjoint_gradient():
+@pytest.mark.parametrize("precond", ["jacobi", "pmg"])
+def test_autograd_matches_oracle_adjoint_gradient(precond):
+    # the forward and the adjoint solve take the same options: Jacobi PCG, or
+    # FP64 flexible CG with the FP32 p-multigrid cycle (k on every level)
     m, fld, M, k, b, target, h2 = _setup(shape=(4, 4, 4), N=5)
+    opts = {}
+    if precond == "pmg":
+        M.setup_pmg()
+        opts = dict(precond="pmg", precond_prec="fp32")
     kk = k.clone().requires_grad_(True)
     bb = b.clone().requires_grad_(True)
-    x = sem.sem_solve(M, bb, k=kk, h2=h2, rtol=1e-13)
+    x = sem.sem_solve(M, bb, k=kk, h2=h2, rtol=1e-13, **opts)
     L = _loss(M, x, target)
     L.backward()
     P = oracle.Problem(m.xyz, m.gid, m.dirichlet, m.N, k=fld["k"], h2=h2)
