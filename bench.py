@@ -11,8 +11,9 @@ value = unique DOF x iterations / second of the timed steps (GDOF/s).
 roofline: the element-operator kernel (the dominant kernel), 64 algorithmic
 bytes per local point (u, six geometric factors, w in FP64) per launch,
 divided by its average duration measured with HIP events on the solve's
-stream inside the timed region (around each operator launch of the last
-timed step; the other steps run without events).
+stream inside the timed region: each operator launch of the last timed step
+is made with a start and a stop event that the runtime stamps with the
+kernel's own start and end (the other steps run without events).
 CPU leg (after every GPU measurement): cpu_baseline, the CPU oracle's PCG
 iteration on a 32x8x16-element sample of the same recipe timed on this host;
 and the error of every solve result against the FP64 oracle: the GPU

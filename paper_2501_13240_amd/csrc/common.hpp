@@ -263,10 +263,12 @@ namespace sem {
 // `skip` (device, nullable): nonzero -> the kernel returns at once
 // `lp` (FP32 only): 0 FP32 contractions, 1 bfloat16 and 2 half operands on
 // the matrix cores (hipErrorInvalidValue for other values or FP64 with lp != 0)
+// ev0 / ev1 (nullable): events stamped with the kernel's own start and end
 template <typename T>
 hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
                      const T* G, const T* B, const T* D, hipStream_t s,
-                     const int32_t* skip = nullptr, int lp = 0);
+                     const int32_t* skip = nullptr, int lp = 0, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr);
 // In-solve operator with split output (matrix-core kernel, N >= 5, FP64 or
 // FP32 contractions): u gathered from the free vector through m->lmap2;
 // results at free nodes with one local copy go straight to wf (free
@@ -279,7 +281,8 @@ hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, c
 template <typename T>
 hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart,
                            const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
-                           const int32_t* skip);
+                           const int32_t* skip, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
 bool ax_split_available(const sem_mesh* m);
 int ax_split_parts(int N);
 // kbar = sign sum_ab (D_a wbar) G_ab (D_b u) at every local point

@@ -38,6 +38,8 @@
 #include <cstring>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "mfma_16x16x4.hpp"
 
@@ -676,41 +678,54 @@ __global__ void mass_kernel(int64_t n, const T* __restrict__ B, const T* __restr
     w[q] = B[q] * u[q];
 }
 
+// A launch that, when ev0 / ev1 are given, has the runtime stamp them with the
+// kernel's own start and end (the solve's operator timing): an event recorded
+// before the launch would also count the dispatch latency.
+#define SEM_LAUNCH(ev0, ev1, kernel, grid, block, stream, ...)                           \
+  do {                                                                                 \
+    if ((ev0) != nullptr || (ev1) != nullptr)                                          \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, ev0, ev1, 0, __VA_ARGS__); \
+    else                                                                               \
+      hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__);                 \
+  } while (0)
+
 template <int N, typename T, int LP>
 hipError_t run_ax_mfma(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
-                       const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip) {
+                       const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip,
+                       hipEvent_t ev0, hipEvent_t ev1) {
   using M = MShape<N>;
   if (lmap)
-    hipLaunchKernelGGL((ax_mfma_kernel<N, T, 1, LP>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                       u, lmap, w, k, h2, G, B, D, m->E, skip, (T*)nullptr, (double*)nullptr);
+    SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 1, LP>), dim3((unsigned)m->E), dim3(M::TPB), s, u,
+               lmap, w, k, h2, G, B, D, m->E, skip, (T*)nullptr, (double*)nullptr);
   else
-    hipLaunchKernelGGL((ax_mfma_kernel<N, T, 0, LP>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                       u, lmap, w, k, h2, G, B, D, m->E, skip, (T*)nullptr, (double*)nullptr);
+    SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 0, LP>), dim3((unsigned)m->E), dim3(M::TPB), s, u,
+               lmap, w, k, h2, G, B, D, m->E, skip, (T*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }
 
 template <int N, typename T>
 hipError_t run_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
-                  const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip, int lp) {
+                  const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip, int lp,
+                  hipEvent_t ev0, hipEvent_t ev1) {
   if constexpr (std::is_same<T, float>::value) {
-    if (lp == 1) return run_ax_mfma<N, float, 1>(m, u, lmap, w, k, h2, G, B, D, s, skip);
-    if (lp == 2) return run_ax_mfma<N, float, 2>(m, u, lmap, w, k, h2, G, B, D, s, skip);
+    if (lp == 1) return run_ax_mfma<N, float, 1>(m, u, lmap, w, k, h2, G, B, D, s, skip, ev0, ev1);
+    if (lp == 2) return run_ax_mfma<N, float, 2>(m, u, lmap, w, k, h2, G, B, D, s, skip, ev0, ev1);
   }
   if (lp != 0) return hipErrorInvalidValue;
   if constexpr (has_mfma(N)) {
     const AxChoice c = ax_choice();
     const bool mfma = c == AxChoice::Auto ? prefer_mfma(N, lmap != nullptr, sizeof(T) == 4)
                                           : c == AxChoice::Mfma;
-    if (mfma) return run_ax_mfma<N, T, 0>(m, u, lmap, w, k, h2, G, B, D, s, skip);
+    if (mfma) return run_ax_mfma<N, T, 0>(m, u, lmap, w, k, h2, G, B, D, s, skip, ev0, ev1);
   }
   using S = Shape<N>;
   const int64_t grid = (m->E + S::EPB - 1) / S::EPB;
   if (lmap)
-    hipLaunchKernelGGL((ax_kernel<N, T, true>), dim3((unsigned)grid), dim3(S::BT), 0, s, u, lmap,
-                       w, k, h2, G, B, D, m->E, skip);
+    SEM_LAUNCH(ev0, ev1, (ax_kernel<N, T, true>), dim3((unsigned)grid), dim3(S::BT), s, u, lmap,
+               w, k, h2, G, B, D, m->E, skip);
   else
-    hipLaunchKernelGGL((ax_kernel<N, T, false>), dim3((unsigned)grid), dim3(S::BT), 0, s, u,
-                       lmap, w, k, h2, G, B, D, m->E, skip);
+    SEM_LAUNCH(ev0, ev1, (ax_kernel<N, T, false>), dim3((unsigned)grid), dim3(S::BT), s, u, lmap,
+               w, k, h2, G, B, D, m->E, skip);
   return hipGetLastError();
 }
 
@@ -729,33 +744,35 @@ hipError_t run_kbar(const sem_mesh* m, const double* u, const double* wb, double
 template <typename T>
 hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, const T* k, T h2,
                      const T* G, const T* B, const T* D, hipStream_t s, const int32_t* skip,
-                     int lp) {
+                     int lp, hipEvent_t ev0, hipEvent_t ev1) {
   switch (m->N) {
-    case 1: return run_ax<1, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 2: return run_ax<2, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 3: return run_ax<3, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 4: return run_ax<4, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 5: return run_ax<5, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 6: return run_ax<6, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 7: return run_ax<7, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 8: return run_ax<8, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 9: return run_ax<9, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
-    case 10: return run_ax<10, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp);
+    case 1: return run_ax<1, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 2: return run_ax<2, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 3: return run_ax<3, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 4: return run_ax<4, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 5: return run_ax<5, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 6: return run_ax<6, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 7: return run_ax<7, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 8: return run_ax<8, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 9: return run_ax<9, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
+    case 10: return run_ax<10, T>(m, u, lmap, w, k, h2, G, B, D, s, skip, lp, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
 template hipError_t launch_ax<double>(const sem_mesh*, const double*, const int32_t*, double*,
                                       const double*, double, const double*, const double*,
-                                      const double*, hipStream_t, const int32_t*, int);
+                                      const double*, hipStream_t, const int32_t*, int, hipEvent_t,
+                                      hipEvent_t);
 template hipError_t launch_ax<float>(const sem_mesh*, const float*, const int32_t*, float*,
                                      const float*, float, const float*, const float*,
-                                     const float*, hipStream_t, const int32_t*, int);
+                                     const float*, hipStream_t, const int32_t*, int, hipEvent_t,
+                                     hipEvent_t);
 
 namespace {
 template <int N, typename T>
 hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart, const T* k,
                         T h2, const T* G, const T* B, const T* D, hipStream_t s,
-                        const int32_t* skip) {
+                        const int32_t* skip, hipEvent_t ev0, hipEvent_t ev1) {
   if constexpr (has_mfma(N)) {
     using M = MShape<N>;
     // shared-copy results stay in the memory-side cache for the segmented
@@ -767,17 +784,17 @@ hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epa
     // without epart: the forms without wavefront sums (MODE 4 / 5)
     const bool plain = m->nL * (int64_t)sizeof(T) <= m->ax_nt_bytes;
     if (epart && plain)
-      hipLaunchKernelGGL((ax_mfma_kernel<N, T, 2, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                         u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+      SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 2, 0>), dim3((unsigned)m->E), dim3(M::TPB), s,
+                 u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
     else if (epart)
-      hipLaunchKernelGGL((ax_mfma_kernel<N, T, 3, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                         u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+      SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 3, 0>), dim3((unsigned)m->E), dim3(M::TPB), s,
+                 u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
     else if (plain)
-      hipLaunchKernelGGL((ax_mfma_kernel<N, T, 4, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                         u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+      SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 4, 0>), dim3((unsigned)m->E), dim3(M::TPB), s,
+                 u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
     else
-      hipLaunchKernelGGL((ax_mfma_kernel<N, T, 5, 0>), dim3((unsigned)m->E), dim3(M::TPB), 0, s,
-                         u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+      SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 5, 0>), dim3((unsigned)m->E), dim3(M::TPB), s,
+                 u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
     return hipGetLastError();
   } else {
     return hipErrorNotSupported;
@@ -811,25 +828,26 @@ bool ax_split_available(const sem_mesh* m) {
 template <typename T>
 hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart,
                            const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
-                           const int32_t* skip) {
+                           const int32_t* skip, hipEvent_t ev0, hipEvent_t ev1) {
   if (!ax_split_available(m)) return hipErrorNotSupported;
   switch (m->N) {
-    case 5: return run_ax_split<5, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
-    case 6: return run_ax_split<6, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
-    case 7: return run_ax_split<7, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
-    case 8: return run_ax_split<8, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
-    case 9: return run_ax_split<9, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
-    case 10: return run_ax_split<10, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip);
+    case 5: return run_ax_split<5, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
+    case 6: return run_ax_split<6, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
+    case 7: return run_ax_split<7, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
+    case 8: return run_ax_split<8, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
+    case 9: return run_ax_split<9, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
+    case 10: return run_ax_split<10, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
     default: return hipErrorNotSupported;
   }
 }
 template hipError_t launch_ax_split<double>(const sem_mesh*, const double*, double*, double*,
                                             double*, const double*, double, const double*,
                                             const double*, const double*, hipStream_t,
-                                            const int32_t*);
+                                            const int32_t*, hipEvent_t, hipEvent_t);
 template hipError_t launch_ax_split<float>(const sem_mesh*, const float*, float*, float*, double*,
                                            const float*, float, const float*, const float*,
-                                           const float*, hipStream_t, const int32_t*);
+                                           const float*, hipStream_t, const int32_t*, hipEvent_t,
+                                           hipEvent_t);
 
 hipError_t launch_ax_kbar(const sem_mesh* m, const double* u, const double* wbar, double* kbar,
                           double sign, hipStream_t s) {

@@ -832,14 +832,14 @@ sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* x
     e0 = W.ev[W.ev_used];
     e1 = W.ev[W.ev_used + 1];
     W.ev_used += 2;
-    SEM_HIP(hipEventRecord(e0, s));
   }
+  // timed: the runtime stamps e0 / e1 with the kernel's own start and end
   hipError_t e =
-      wf ? launch_ax_split<T>(m, xf, wf, wL, epart, op.k, op.h2, op.G, op.B, op.D, s, op.skip)
+      wf ? launch_ax_split<T>(m, xf, wf, wL, epart, op.k, op.h2, op.G, op.B, op.D, s, op.skip,
+                              e0, e1)
          : launch_ax<T>(m, xf, m->lmap.as<int32_t>(), wL, op.k, op.h2, op.G, op.B, op.D, s,
-                        op.skip, op.lp);
+                        op.skip, op.lp, e0, e1);
   if (e != hipSuccess) return hip_fail(e, "operator kernel");
-  if (timed) SEM_HIP(hipEventRecord(e1, s));
   return SEM_OK;
 }
 template sem_status apply_op<double>(const sem_mesh*, SolveWork&, const Op<double>&, const double*,
