@@ -318,8 +318,8 @@ def pmg_cube_iteration_bytes(nel=32, orders=(9, 4, 2, 1), smooth_order=4, coarse
     # outer FP64 flexible CG
     nL, nf, n1, _, _ = sizes(orders[0])
     add("ax FP64 in-solve (64 B per local point)", 64.0 * nL)
-    add("shared-node sum (12 B per shared copy, 20 B per shared node)",
-        12.0 * (nL - n1) + 20.0 * (nf - n1))
+    add("shared-node sum (12 B per shared copy, 12 B per shared node)",
+        12.0 * (nL - n1) + 12.0 * (nf - n1))
     add("CG update (48 B per free node)", 48.0 * nf)
     add("residual to FP32 (12 B per free node)", 12.0 * nf)
     add("z and dots (28 B per free node)", 28.0 * nf)

@@ -273,14 +273,15 @@ hipError_t launch_ax(const sem_mesh* m, const T* u, const int32_t* lmap, T* w, c
 // FP32 contractions): u gathered from the free vector through m->lmap2;
 // results at free nodes with one local copy go straight to wf (free
 // vector), at shared free nodes to wL at e P + surface_rank (local, for the
-// segmented sum over [n_single, n_free) through fperm2); epart[3 (parts e +
-// i) + {0, 1, 2}] (parts = ax_split_parts(N), one per wavefront i) = the
-// sums of u w, w and u over the single-copy nodes (nullable: then no sums
-// are formed).  hipErrorNotSupported when unavailable (see
-// ax_split_available).
+// segmented sum over [n_single, n_free) through fperm2); epart[2 (parts e +
+// i) + {0, 1}] (parts = ax_split_parts(N), one per wavefront i) = that
+// wavefront's sums of u w and of w over its free copies; with mean_sums
+// false only entry 0 (u w) is written (sum(w) serves the null-space
+// projection alone).  epart nullable: then no sums are formed.
+// hipErrorNotSupported when unavailable (see ax_split_available).
 template <typename T>
 hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart,
-                           const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
+                           bool mean_sums, const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
                            const int32_t* skip, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr);
 bool ax_split_available(const sem_mesh* m);

@@ -332,13 +332,16 @@ struct MShape {
 // through lmap.  MODE 2 (in-solve split): lmap holds v >= 0 for a free node v
 // with one local copy, -(v + 2) for a shared free node v, -1 for a Dirichlet
 // copy; single-copy results go straight to the free vector wf[v], shared
-// copies' results to w (local, for the segmented sum), and epart[3 (NW e +
-// wave) + a] receives each wavefront's sums of p w and w over all its free
-// copies and of p over its single-copy nodes (p = the gathered input),
-// reduced in a fixed order.  MODE 3: MODE 2 with nontemporal shared-copy
-// stores (for local arrays larger than the memory-side cache).  MODE 4 / 5:
-// MODE 2 / 3 without the wavefront sums (a Chebyshev pass needs none; they
-// cost the FP32 N = 9 operator 10 %).
+// copies' results to w (local, for the segmented sum), and epart[2 (NW e +
+// wave) + a] receives each wavefront's sums of p w and of w over all its
+// free copies (p = the gathered input; over the copies of a shared node
+// they add up to p_g w_g and w_g), reduced in a fixed order.  MODE 3: MODE 2
+// with nontemporal shared-copy stores (for local arrays larger than the
+// memory-side cache).  MODE 4 / 5: MODE 2 / 3 without the wavefront sums (a
+// Chebyshev pass needs none).  MODE 6 / 7: MODE 2 / 3 with p w only (sum(w)
+// serves the null-space projection alone).  Each sum costs the kernel more
+// than its instructions suggest (measured per launch, N = 9 FP64: no sums
+// 375 us, p w 390 us, three sums 440-460 us; N = 7 FP64: 89, 92, 95 us).
 // Waves per SIMD the split in-solve form asks for: the gather form's
 // occupancy at N = 6 and N = 9, which a few extra registers would cost it
 // (at N = 9, with 512-thread workgroups, one fewer resident workgroup per CU
@@ -356,8 +359,10 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
   constexpr int n1 = S::n1, P = S::P, TPB = S::TPB, PPT = S::PPT, NT = S::NT, KS = S::KS,
                 NW = S::NW;
   static_assert(LP == 0 || std::is_same<T, float>::value, "16-bit operands need FP32 data");
-  constexpr bool kDots = (MODE == 2 || MODE == 3);       // wavefront sums into epart
-  constexpr bool kNtShared = (MODE == 3 || MODE == 5);   // nontemporal shared-copy stores
+  // wavefront sums into epart: 2 (p w, w) or 1 (p w)
+  constexpr int kSums = (MODE == 2 || MODE == 3) ? 2 : (MODE == 6 || MODE == 7) ? 1 : 0;
+  constexpr bool kDots = kSums > 0;
+  constexpr bool kNtShared = (MODE == 3 || MODE == 5 || MODE == 7);  // nontemporal shared-copy stores
   constexpr bool kScale = LP == 2;
   if (skip && *skip) return;  // uniform over the grid
   __shared__ T su[P];
@@ -537,7 +542,7 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
       contract_tile16<n1, LP, 2, true>(sa[2], so, at16, tile, lane, sc[2], 1.0f / sc[2]);
   }
   __syncthreads();
-  double ps[3] = {0.0, 0.0, 0.0};
+  double ps[2] = {0.0, 0.0};
   (void)ps;
 #pragma unroll
   for (int s = 0; s < PPT; ++s) {
@@ -550,23 +555,18 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
         const int32_t c = scode[q];
         if (c >= 0) {
           st_stream(acc, wf + c);
-          if constexpr (kDots) {
-            ps[0] += (double)uq[s] * (double)acc;
-            ps[1] += (double)acc;
-            ps[2] += (double)uq[s];
-          }
         } else if (c <= -2) {
-          // shared copy: at its surface slot of the element's block.  Its
-          // share of p.w and sum(w): over all copies these add up to p_g w_g
-          // and w_g (sum(p) over the shared nodes is left to the segmented sum)
+          // shared copy: at its surface slot of the element's block
           T* dst = w + e * P + surface_rank(q % n1, (q / n1) % n1, q / (n1 * n1), N);
           if constexpr (kNtShared)
             st_stream(acc, dst);
           else
             *dst = acc;
-          if constexpr (kDots) {
+        }
+        if constexpr (kDots) {
+          if (c != -1) {  // free copies only
             ps[0] += (double)uq[s] * (double)acc;
-            ps[1] += (double)acc;
+            if constexpr (kSums == 2) ps[1] += (double)acc;
           }
         }
       } else {
@@ -575,14 +575,17 @@ __global__ __launch_bounds__(MShape<N>::TPB) __attribute__((
     }
   }
   if constexpr (kDots) {
-    // one triple of sums per wavefront: no barrier, no LDS.  Lane 0 is found
-    // by mbcnt here rather than from the lane index computed at the start,
+    // the sums of one wavefront: no barrier, no LDS.  Lane 0 is found by
+    // mbcnt here rather than from the lane index computed at the start,
     // which the compiler would otherwise keep (and at N = 9 spill) all along.
+    // (Tried and not kept: the sums on the matrix cores, 16 instead of 30
+    // vector instructions per sum, and the three DPP chains interleaved:
+    // both as slow or slower.)
     const bool first_lane = __builtin_amdgcn_mbcnt_lo(~0u, 0u) == 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < kSums; ++a) {
       const double x = wave_sum_d(ps[a]);
-      if (first_lane) epart[(e * NW + wv) * 3 + a] = x;
+      if (first_lane) epart[(e * NW + wv) * 2 + a] = x;
     }
   }
 }
@@ -770,8 +773,8 @@ template hipError_t launch_ax<float>(const sem_mesh*, const float*, const int32_
 
 namespace {
 template <int N, typename T>
-hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart, const T* k,
-                        T h2, const T* G, const T* B, const T* D, hipStream_t s,
+hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart, bool mean_sums,
+                        const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
                         const int32_t* skip, hipEvent_t ev0, hipEvent_t ev1) {
   if constexpr (has_mfma(N)) {
     using M = MShape<N>;
@@ -779,22 +782,28 @@ hipError_t run_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epa
     // sum when the local array fits well inside it (256 MB): plain stores up
     // to m->ax_nt_bytes, 128 MB by default (the 32x32x16, N = 7 box: 67 MB,
     // 1.1 % faster per iteration), nontemporal above (the 32^3, N = 9 cube:
-    // 262 MB, 2.2 %) (MODE 2 plain, MODE 3 nontemporal: a run-time switch in
-    // the kernel cost what the nontemporal stores save)
-    // without epart: the forms without wavefront sums (MODE 4 / 5)
+    // 262 MB, 2.2 %) (a run-time switch in the kernel cost what the
+    // nontemporal stores save).  Sums: p w and sum(w) (MODE 2 / 3) when the
+    // solve projects out the constants, p w alone (MODE 6 / 7) otherwise,
+    // none without epart (MODE 4 / 5).
     const bool plain = m->nL * (int64_t)sizeof(T) <= m->ax_nt_bytes;
-    if (epart && plain)
-      SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 2, 0>), dim3((unsigned)m->E), dim3(M::TPB), s,
-                 u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
-    else if (epart)
-      SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 3, 0>), dim3((unsigned)m->E), dim3(M::TPB), s,
-                 u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
-    else if (plain)
-      SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 4, 0>), dim3((unsigned)m->E), dim3(M::TPB), s,
-                 u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
-    else
-      SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, 5, 0>), dim3((unsigned)m->E), dim3(M::TPB), s,
-                 u, m->lmap2.as<int32_t>(), wL, k, h2, G, B, D, m->E, skip, wf, epart);
+    const int mode = !epart ? (plain ? 4 : 5) : mean_sums ? (plain ? 2 : 3) : (plain ? 6 : 7);
+    const dim3 grid((unsigned)m->E), block(M::TPB);
+    const int32_t* lm = m->lmap2.as<int32_t>();
+#define SEM_SPLIT_CASE(MD)                                                                   \
+  case MD:                                                                                   \
+    SEM_LAUNCH(ev0, ev1, (ax_mfma_kernel<N, T, MD, 0>), grid, block, s, u, lm, wL, k, h2, G, B, \
+               D, m->E, skip, wf, epart);                                                    \
+    break;
+    switch (mode) {
+      SEM_SPLIT_CASE(2)
+      SEM_SPLIT_CASE(3)
+      SEM_SPLIT_CASE(4)
+      SEM_SPLIT_CASE(5)
+      SEM_SPLIT_CASE(6)
+      SEM_SPLIT_CASE(7)
+    }
+#undef SEM_SPLIT_CASE
     return hipGetLastError();
   } else {
     return hipErrorNotSupported;
@@ -827,25 +836,31 @@ bool ax_split_available(const sem_mesh* m) {
 
 template <typename T>
 hipError_t launch_ax_split(const sem_mesh* m, const T* u, T* wf, T* wL, double* epart,
-                           const T* k, T h2, const T* G, const T* B, const T* D, hipStream_t s,
-                           const int32_t* skip, hipEvent_t ev0, hipEvent_t ev1) {
+                           bool mean_sums, const T* k, T h2, const T* G, const T* B, const T* D,
+                           hipStream_t s, const int32_t* skip, hipEvent_t ev0, hipEvent_t ev1) {
   if (!ax_split_available(m)) return hipErrorNotSupported;
   switch (m->N) {
-    case 5: return run_ax_split<5, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
-    case 6: return run_ax_split<6, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
-    case 7: return run_ax_split<7, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
-    case 8: return run_ax_split<8, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
-    case 9: return run_ax_split<9, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
-    case 10: return run_ax_split<10, T>(m, u, wf, wL, epart, k, h2, G, B, D, s, skip, ev0, ev1);
+    case 5: return run_ax_split<5, T>(m, u, wf, wL, epart, mean_sums, k, h2, G, B, D, s, skip,
+                                           ev0, ev1);
+    case 6: return run_ax_split<6, T>(m, u, wf, wL, epart, mean_sums, k, h2, G, B, D, s, skip,
+                                           ev0, ev1);
+    case 7: return run_ax_split<7, T>(m, u, wf, wL, epart, mean_sums, k, h2, G, B, D, s, skip,
+                                           ev0, ev1);
+    case 8: return run_ax_split<8, T>(m, u, wf, wL, epart, mean_sums, k, h2, G, B, D, s, skip,
+                                           ev0, ev1);
+    case 9: return run_ax_split<9, T>(m, u, wf, wL, epart, mean_sums, k, h2, G, B, D, s, skip,
+                                           ev0, ev1);
+    case 10: return run_ax_split<10, T>(m, u, wf, wL, epart, mean_sums, k, h2, G, B, D, s, skip,
+                                           ev0, ev1);
     default: return hipErrorNotSupported;
   }
 }
 template hipError_t launch_ax_split<double>(const sem_mesh*, const double*, double*, double*,
-                                            double*, const double*, double, const double*,
+                                            double*, bool, const double*, double, const double*,
                                             const double*, const double*, hipStream_t,
                                             const int32_t*, hipEvent_t, hipEvent_t);
 template hipError_t launch_ax_split<float>(const sem_mesh*, const float*, float*, float*, double*,
-                                           const float*, float, const float*, const float*,
+                                           bool, const float*, float, const float*, const float*,
                                            const float*, hipStream_t, const int32_t*, hipEvent_t,
                                            hipEvent_t);
 

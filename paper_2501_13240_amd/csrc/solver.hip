@@ -105,7 +105,7 @@ __device__ __forceinline__ bool finite(double x) { return x == x && fabs(x) <= 1
 // in two slots indexed by the iteration's parity so that block 0 can store
 // the next value while other blocks still read the current one.
 
-// w = R Q^T w_L (segmented sum); partials of p.w, sum(w), sum(p)
+// w = R Q^T w_L (segmented sum); partials of p.w and sum(w)
 template <typename T>
 __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t* __restrict__ seg,
                                                        const int32_t* __restrict__ perm,
@@ -116,51 +116,46 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t
   // the previous iteration's direction update has completed
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->pending = 0;
   if (sc->done) return;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[2] = {0.0, 0.0};
   BLOCK_CHUNK(g, nf) {
     const T s = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
     w[g] = s;
-    const double pg = (double)p[g];
-    v[0] += pg * (double)s;
+    v[0] += (double)p[g] * (double)s;
     v[1] += (double)s;
-    v[2] += pg;
   }
-  block_partials<3>(v, part);
+  block_partials<2>(v, part);
 }
 
 // The same for the split operator, which has already written w at the
-// single-copy free nodes [0, n1) and the partial sums (ne triples, one per
-// wavefront of each element; p.w and sum(w) over all copies, sum(p) over the
-// single-copy nodes): segmented sums over the shared free nodes [n1, nf)
-// only, plus this block's chunk of the partial triples (in order, so the
-// totals stay deterministic).
+// single-copy free nodes [0, n1) and the partial sums (ne pairs, one per
+// wavefront of each element: p.w and sum(w) over all its copies, p.w alone
+// without the null-space projection): segmented sums over the shared free
+// nodes [n1, nf) only, plus this block's chunk of the partial pairs (in
+// order, so the totals stay deterministic).
 template <typename T>
 __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
     int64_t n1, int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
-    const T* __restrict__ wL, const T* __restrict__ p, T* __restrict__ w, int64_t ne,
-    const double* __restrict__ epart, double* __restrict__ part, CgScalars* __restrict__ sc) {
+    const T* __restrict__ wL, T* __restrict__ w, int64_t ne, const double* __restrict__ epart,
+    double* __restrict__ part, CgScalars* __restrict__ sc) {
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->pending = 0;
   if (sc->done) return;
-  double v[3] = {0.0, 0.0, 0.0};
+  // sum(w) serves the null-space projection only
+  const bool mean = sc->neumann != 0;
+  double v[2] = {0.0, 0.0};
   {
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t ch = (ne + gridDim.x - 1) / gridDim.x;
     const int64_t lo = lb * ch, hi = lo + ch < ne ? lo + ch : ne;
     for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-      v[0] += epart[3 * e];
-      v[1] += epart[3 * e + 1];
-      v[2] += epart[3 * e + 2];
+      v[0] += epart[2 * e];
+      if (mean) v[1] += epart[2 * e + 1];
     }
   }
-  // the operator's triples already hold p.w and sum(w) over every copy;
-  // sum(p) over the shared nodes is needed for the null-space projection only
-  const bool sum_p = sc->neumann != 0;
   BLOCK_CHUNK(i, nf - n1) {
     const int64_t g = n1 + i;
     w[g] = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
-    if (sum_p) v[2] += (double)p[g];
   }
-  block_partials<3>(v, part);
+  block_partials<2>(v, part);
 }
 
 // What the residual vector of a CG iteration holds, and which partials the
@@ -179,8 +174,11 @@ __device__ __forceinline__ bool aligned16(const void* a, const void* b, const vo
   return (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) == 0;
 }
 
-// alpha = rho / (p.w - mean_w sum(p)) from the p.w, sum(w), sum(p) partials,
-// the same in every block; block 0 records alpha, mean_w and the iteration in
+// alpha = rho / p.w and, for the null-space projection, mean_w = sum(w) / n
+// from the p.w and sum(w) partials (sum(w) vanishes up to rounding, as A
+// annihilates the constants: subtracting mean_w keeps r exactly free of them,
+// as the projection of r after each update does), the same in every block;
+// block 0 records alpha, mean_w and the iteration in
 // progress (the iteration index lives on the device, so a captured chunk of
 // iterations can be replayed: only later kernels advance it).  False on a
 // breakdown (p.w <= 0 or not finite), which ends the solve.
@@ -188,14 +186,10 @@ __device__ __forceinline__ bool cg_alpha(const double* __restrict__ part_in, int
                                          CgScalars* __restrict__ sc, double* __restrict__ ahist,
                                          bool set_pending, double& alpha, double& mw) {
   const int kit = sc->it;
-  double S[3];
-  block_total<3>(part_in, nblk, S);
-  double pw = S[0];
-  mw = 0.0;
-  if (sc->neumann) {
-    mw = S[1] * sc->inv_n;
-    pw -= mw * S[2];
-  }
+  double S[2];
+  block_total<2>(part_in, nblk, S);
+  const double pw = S[0];
+  mw = sc->neumann ? S[1] * sc->inv_n : 0.0;
   if (!(pw > 0.0) || !finite(pw)) {  // same decision in every block
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->status = 2;
@@ -819,7 +813,7 @@ static sem_status remove_mean(const sem_mesh* m, SolveWork& W, T* a, hipStream_t
 
 template <typename T>
 sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* xf, T* wL,
-                    hipStream_t s, bool timed, T* wf, double* epart) {
+                    hipStream_t s, bool timed, T* wf, double* epart, bool mean_sums) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     if (W.ev_used + 2 > (int)W.ev.size()) {
@@ -835,17 +829,17 @@ sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* x
   }
   // timed: the runtime stamps e0 / e1 with the kernel's own start and end
   hipError_t e =
-      wf ? launch_ax_split<T>(m, xf, wf, wL, epart, op.k, op.h2, op.G, op.B, op.D, s, op.skip,
-                              e0, e1)
+      wf ? launch_ax_split<T>(m, xf, wf, wL, epart, mean_sums, op.k, op.h2, op.G, op.B, op.D, s,
+                              op.skip, e0, e1)
          : launch_ax<T>(m, xf, m->lmap.as<int32_t>(), wL, op.k, op.h2, op.G, op.B, op.D, s,
                         op.skip, op.lp, e0, e1);
   if (e != hipSuccess) return hip_fail(e, "operator kernel");
   return SEM_OK;
 }
 template sem_status apply_op<double>(const sem_mesh*, SolveWork&, const Op<double>&, const double*,
-                                     double*, hipStream_t, bool, double*, double*);
+                                     double*, hipStream_t, bool, double*, double*, bool);
 template sem_status apply_op<float>(const sem_mesh*, SolveWork&, const Op<float>&, const float*,
-                                    float*, hipStream_t, bool, float*, double*);
+                                    float*, hipStream_t, bool, float*, double*, bool);
 
 // ------------------------------------------------------ Chebyshev on device
 
@@ -1050,7 +1044,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   // single-copy free nodes leave the operator directly (see launch_ax_split)
   const bool split = op_it.lp == 0 && ax_split_available(m);
   const int64_t nparts = split ? m->E * ax_split_parts(m->N) : 0;
-  double* epart = split ? W.vec<double>(W.epart, 3 * nparts) : nullptr;
+  double* epart = split ? W.vec<double>(W.epart, 2 * nparts) : nullptr;
   if (split && !epart) return fail(SEM_ENOMEM, "work space");
   // Chebyshev fused into the iteration's kernels (needs the split operator)
   const ChebFuse<Tp>& fu = a.fuse;
@@ -1074,8 +1068,8 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
     hipLaunchKernelGGL((k_update_cheb0<T, Tp>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
                        fu.dinv, fd, fc0, partA, (int)nb, partB, sc, ahist);
     for (int k = 1; k < fu.order; ++k) {
-      const hipError_t he = launch_ax_split<Tp>(m, fd, fwf, fwL, nullptr, fop.k, fop.h2, fop.G,
-                                                fop.B, fop.D, ss, fop.skip);
+      const hipError_t he = launch_ax_split<Tp>(m, fd, fwf, fwL, nullptr, false, fop.k, fop.h2,
+                                                fop.G, fop.B, fop.D, ss, fop.skip);
       if (he != hipSuccess) return hip_fail(he, "Chebyshev operator");
       const bool first = (k == 1), last = (k == fu.order - 1);
 #define SEM_FSTEP(F, L)                                                                        \
@@ -1095,9 +1089,9 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   auto iteration = [&](hipStream_t ss) -> sem_status {
     sem_status e;
     if (split) {
-      if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile, w, epart))) return e;
+      if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile, w, epart, a.neumann))) return e;
       hipLaunchKernelGGL((k_gsum_split_pw<T>), dim3(nb), dim3(kVecBlock), 0, ss, m->n_single,
-                         nf, m->fseg.as<int32_t>(), m->fperm2.as<int32_t>(), wL, p, w, nparts,
+                         nf, m->fseg.as<int32_t>(), m->fperm2.as<int32_t>(), wL, w, nparts,
                          epart, partA, sc);
     } else {
       if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile))) return e;

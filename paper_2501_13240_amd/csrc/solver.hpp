@@ -114,7 +114,8 @@ struct CgArgs {
 
 template <typename T>
 sem_status apply_op(const sem_mesh* m, SolveWork& W, const Op<T>& op, const T* xf, T* wL,
-                    hipStream_t s, bool timed, T* wf = nullptr, double* epart = nullptr);
+                    hipStream_t s, bool timed, T* wf = nullptr, double* epart = nullptr,
+                    bool mean_sums = true);
 
 // work vectors of one Chebyshev pass: d, r_k (free, n_free) and w_L (local, n_L)
 template <typename Tp>
