@@ -119,6 +119,28 @@ __global__ void k_seg_dec(int64_t nf, const int32_t* __restrict__ seg,
   GRID_STRIDE(g, nf) r[g] -= segment_sum<T>(perm, vL, seg[g], seg[g + 1]);
 }
 
+// The same residuals from the split operator's output (levels of order >= 5
+// that carry its routing): w at the single-copy nodes [0, n1) is read from
+// wf, contiguous; only the shared nodes [n1, nf) sum their copies, from the
+// elements' surface slots.  SUB: r = b - A d; else r -= A d.  Every block
+// takes a chunk of each range, so the segmented sums are spread over all.
+template <typename T, bool SUB>
+__global__ __launch_bounds__(kVecBlock) void k_split_res(
+    int64_t n1, int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
+    const T* __restrict__ wf, const T* __restrict__ wL, const T* __restrict__ b,
+    T* __restrict__ r, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  {
+    BLOCK_CHUNK(g, n1) r[g] = (SUB ? b[g] : r[g]) - wf[g];
+  }
+  {
+    BLOCK_CHUNK(i, nf - n1) {
+      const int64_t g = n1 + i;
+      r[g] = (SUB ? b[g] : r[g]) - segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_vadd(int64_t n, T* __restrict__ x, const T* __restrict__ y,
                        const int32_t* __restrict__ skip) {
@@ -184,6 +206,46 @@ T* box_of(const SchwarzDev& X) {
   else return X.box32.as<float>();
 }
 
+// r = b - A d (sub) or r -= A d on one level: the split operator and
+// k_split_res where the level carries the split routing (order >= 5: the
+// single-copy nodes skip the gather of their copies), else the gather form
+// and a segmented sum over all free nodes
+template <typename T>
+sem_status level_residual(Pmg& P, PmgLevel& L, const Op<T>& op, const T* d, const T* b, T* r,
+                          bool sub, const int32_t* skip, hipStream_t s) {
+  const sem_mesh* m = L.m;
+  SolveWork& W = *m->work;
+  const int64_t nf = m->n_free;
+  T* wL = local_scratch<T>(m);
+  if (!wL) return fail(SEM_ENOMEM, "multigrid work space");
+  sem_status st;
+  if (op.lp == 0 && ax_split_available(m)) {
+    T* wf = P.vec<T>(L, 7);
+    if (!wf) return fail(SEM_ENOMEM, "multigrid work space");
+    if ((st = apply_op<T>(m, W, op, d, wL, s, false, wf, nullptr))) return st;
+    const int32_t* seg = m->fseg.as<int32_t>();
+    const int32_t* perm = m->fperm2.as<int32_t>();
+    if (sub)
+      hipLaunchKernelGGL((k_split_res<T, true>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s,
+                         m->n_single, nf, seg, perm, wf, wL, b, r, skip);
+    else
+      hipLaunchKernelGGL((k_split_res<T, false>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s,
+                         m->n_single, nf, seg, perm, wf, wL, b, r, skip);
+  } else {
+    if ((st = apply_op<T>(m, W, op, d, wL, s, false))) return st;
+    const int32_t* seg = m->fseg.as<int32_t>();
+    const int32_t* perm = m->fperm.as<int32_t>();
+    if (sub)
+      hipLaunchKernelGGL((k_seg_sub<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf, seg, perm,
+                         wL, b, r, skip);
+    else
+      hipLaunchKernelGGL((k_seg_dec<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf, seg, perm,
+                         wL, r, skip);
+  }
+  SEM_CHECK_LAUNCH("level residual");
+  return SEM_OK;
+}
+
 // z = S r: local fast-diagonalisation solves, then the sum over box copies
 template <typename T>
 sem_status schwarz_apply(const PmgLevel& L, const T* r, T* z, const int32_t* skip,
@@ -205,14 +267,12 @@ template <typename T>
 sem_status cheb_schwarz(Pmg& P, PmgLevel& L, const T* r, T* z, const CgScalars* outer,
                         hipStream_t s, int* applies) {
   const sem_mesh* m = L.m;
-  SolveWork& W = *m->work;
   const int64_t nf = m->n_free;
   const int32_t* skip = outer ? &outer->done : nullptr;
   T* d = P.vec<T>(L, 5);
   T* rk = P.vec<T>(L, 6);
-  T* wL = local_scratch<T>(m);
   T* box = box_of<T>(L.sch);
-  if (!d || !rk || !wL) return fail(SEM_ENOMEM, "multigrid work space");
+  if (!d || !rk) return fail(SEM_ENOMEM, "multigrid work space");
   if (!box) return fail(SEM_EINVAL, "Schwarz factors missing");
   Op<T> op = op_of<T>(L);
   op.skip = skip;
@@ -224,14 +284,8 @@ sem_status cheb_schwarz(Pmg& P, PmgLevel& L, const T* r, T* z, const CgScalars* 
   hipLaunchKernelGGL((k_schw_sum_cheb<T, true>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
                      xseg, xperm, box, d, z, (T)(4.0 / (3.0 * lmax)), T(0), skip);
   for (int k = 1; k < P.smooth_order; ++k) {
-    if ((st = apply_op<T>(m, W, op, d, wL, s, false))) return st;
+    if ((st = level_residual<T>(P, L, op, d, r, rk, k == 1, skip, s))) return st;
     if (applies) ++*applies;
-    if (k == 1)
-      hipLaunchKernelGGL((k_seg_sub<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
-                         m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, r, rk, skip);
-    else
-      hipLaunchKernelGGL((k_seg_dec<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
-                         m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, rk, skip);
     SEM_HIP(launch_fdm<T>(L.sch, m->E, rk, box, skip, s));
     const double ca = (2.0 * k - 1.0) / (2.0 * k + 3.0);
     const double cb = (8.0 * k + 4.0) / ((2.0 * k + 3.0) * lmax);
@@ -279,10 +333,8 @@ sem_status vcycle(Pmg& P, int l, const T* r, T* x, const CgScalars* outer, hipSt
   // pre-smoothing
   if ((st = smooth<T>(P, L, r, x, outer, s, applies))) return st;
   // t = r - A x, restricted to the next level
-  if ((st = apply_op<T>(m, W, ops, x, wL, s, false))) return st;
+  if ((st = level_residual<T>(P, L, ops, x, r, t, true, skip, s))) return st;
   if (applies) ++*applies;
-  hipLaunchKernelGGL((k_seg_sub<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
-                     m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, r, t, skip);
   PmgLevel& C = P.lv[l + 1];
   const sem_mesh* mc = C.m;
   T* cL = local_scratch<T>(mc);
@@ -302,10 +354,8 @@ sem_status vcycle(Pmg& P, int l, const T* r, T* x, const CgScalars* outer, hipSt
                      m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, x, skip);
   SEM_CHECK_LAUNCH("prolongation");
   // post-smoothing on t = r - A x
-  if ((st = apply_op<T>(m, W, ops, x, wL, s, false))) return st;
+  if ((st = level_residual<T>(P, L, ops, x, r, t, true, skip, s))) return st;
   if (applies) ++*applies;
-  hipLaunchKernelGGL((k_seg_sub<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf,
-                     m->fseg.as<int32_t>(), m->fperm.as<int32_t>(), wL, r, t, skip);
   if ((st = smooth<T>(P, L, t, u, outer, s, applies))) return st;
   hipLaunchKernelGGL((k_vadd<T>), dim3(grid_for(nf)), dim3(kVecBlock), 0, s, nf, x, u, skip);
   SEM_CHECK_LAUNCH("post-smoothing");
