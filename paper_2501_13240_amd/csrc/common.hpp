@@ -201,16 +201,18 @@ __device__ __forceinline__ Tacc segment_sum(const int32_t* __restrict__ perm,
 // N), then the k = N layer; -1 for an interior point.  The surface has
 // 2 (N+1)^2 + 4 N (N-1) points.  The in-solve operator stores shared copies
 // at this position of the element's local block (see launch_ax_split).
+// Written as selects rather than early returns: the operator evaluates it per
+// point in its stores, where branches cost the FP32 kernel several percent.
 __host__ __device__ inline int surface_rank(int i, int j, int k, int N) {
   const int n = N + 1;
-  if (k == 0) return j * n + i;
-  if (k == N) return n * n + (N - 1) * 4 * N + j * n + i;
   const int base = n * n + (k - 1) * 4 * N;
-  if (j == 0) return base + i;
-  if (j == N) return base + n + 2 * (N - 1) + i;
-  if (i == 0) return base + n + 2 * (j - 1);
-  if (i == N) return base + n + 2 * (j - 1) + 1;
-  return -1;
+  int r = base + n + 2 * (j - 1) + (i == N ? 1 : 0);  // end points of rows 1..N-1
+  r = (i == 0 || i == N) ? r : -1;
+  r = j == N ? base + n + 2 * (N - 1) + i : r;
+  r = j == 0 ? base + i : r;
+  r = k == N ? n * n + (N - 1) * 4 * N + j * n + i : r;
+  r = k == 0 ? j * n + i : r;
+  return r;
 }
 __host__ __device__ constexpr int surface_points(int N) {
   return 2 * (N + 1) * (N + 1) + 4 * N * (N - 1);
