@@ -220,9 +220,32 @@ def true_rel_residual(sem, M, b, x, k=None, h2=0.0):
     return float(torch.sqrt(torch.sum(r * r / mult) / torch.sum(bb * bb / mult)))
 
 
-def mixed_vs_fp64(sem, only=""):
+def ax_rate(sem, M, dtype, reps):
+    """Stand-alone sem_ax on a mesh: median of individually event-timed applies
+    after 5 warm-ups; algorithmic bytes 64 (FP64) or 32 (FP32) per local point."""
+    import torch
+    u = torch.randn(M.E, M.P, dtype=dtype, device="cuda")
+    w = torch.empty_like(u)
+    for _ in range(5):
+        sem.ax(M, u, out=w)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record()
+        sem.ax(M, u, out=w)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+    nbytes = (64.0 if dtype == torch.float64 else 32.0) * M.info["n_local"]
+    return {"us": ms * 1e3, "gdof_s": M.info["n_unique"] / (ms * 1e-3) / 1e9,
+            "algorithmic_bytes": nbytes, "gb_s": nbytes / (ms * 1e-3) / 1e9,
+            "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+
+
+def mixed_vs_fp64(sem, only="", reps=20):
     """Time to ||b - A x|| <= 1e-10 ||b|| on the 32^3-element, N = 9,
-    all-Neumann box: FP64 Jacobi CG against the mixed-precision variants."""
+    all-Neumann box: FP64 Jacobi CG against the mixed-precision variants; and
+    the stand-alone operator's rate on that mesh."""
     import torch
     from sem_inputs import config_mesh
 
@@ -252,6 +275,10 @@ def mixed_vs_fp64(sem, only=""):
     out = {"workload": "32x32x32 hexahedra, N=9, tanh 1:20 z-clustering, seeded wall-preserving "
                        "deformation, all-Neumann (constant mode removed), zero-mean random rhs",
            "n_unique": M.info["n_unique"], "rtol": 1e-10}
+    out["ax_fp64"] = ax_rate(sem, M, torch.float64, reps)
+    out["ax_fp32"] = ax_rate(sem, M, torch.float32, reps)
+    log(f"  sem_ax N = 9: FP64 {out['ax_fp64']['us']:.1f} us ({out['ax_fp64']['hbm_frac']:.3f}), "
+        f"FP32 {out['ax_fp32']['us']:.1f} us ({out['ax_fp32']['hbm_frac']:.3f})")
     sem.lmax_estimate(M)  # bound estimate shared by the Chebyshev variants (cached)
     for name, v in variants.items():
         pmg_setup(sem, M, b, name)
@@ -338,7 +365,15 @@ def pmg_cube_iteration_bytes(nel=32, orders=(9, 4, 2, 1), smooth_order=4, coarse
             2 * m * E * (12.0 * bp + 4.0 * (3 * (N + 3) ** 2 + 3 * (N + 3))))
         add("Schwarz sums with the recurrence (8 B per box copy + 12 / 20 B per node)",
             2 * (8.0 * bc + 12.0 * nf) + 2 * (m - 1) * (8.0 * bc + 20.0 * nf))
-        add("residual sums (8 B per local copy + 12 B per node)", (2 * (m - 1) + 2) * (8.0 * nL + 12.0 * nf))
+        if N >= 5:
+            # split-form residual: wf and r (or b) at single-copy nodes, 8 B per
+            # shared copy, 8 B per shared node, r written
+            add("residual, split form (8 B per single-copy node, 8 B per shared copy and "
+                "shared node, 4 B written per node)",
+                (2 * (m - 1) + 2) * (8.0 * n1 + 8.0 * (nL - n1) + 8.0 * (nf - n1) + 4.0 * nf))
+        else:
+            add("residual sums (8 B per local copy + 12 B per node)",
+                (2 * (m - 1) + 2) * (8.0 * nL + 12.0 * nf))
         nLc, nfc = sizes(orders[lev + 1])[:2]
         add("restriction (4 B per fine point, 8 per fine node, 4 per coarse point; then 8 B "
             "per coarse copy + 8 per coarse node)",
@@ -754,7 +789,7 @@ def main():
     if not args.no_mixed:
         log("mixed vs FP64 on the 32^3, N=9 Neumann box ...")
         M.close()
-        out["mixed_vs_fp64"] = mixed_vs_fp64(sem, args.mixed_variants)
+        out["mixed_vs_fp64"] = mixed_vs_fp64(sem, args.mixed_variants, args.ax_reps)
     M.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
