@@ -183,21 +183,32 @@ def ax_kernel_name(N):
     return "ax_mfma_kernel"
 
 
-def counter_traffic():
-    """HBM bytes per operator launch from the committed rocprofv3 counter summary,
-    or None when the operator source changed since the counters were taken."""
+# the operator kernel's sources: the counter summary holds for them only
+OPERATOR_SOURCES = ("kernels_ax.hip", "common.hpp", "mfma_16x16x4.hpp")
+
+
+def operator_sources_sha256():
+    """sha256 over the operator kernel's source files, in OPERATOR_SOURCES order."""
     import hashlib
 
+    h = hashlib.sha256()
+    for name in OPERATOR_SOURCES:
+        with open(os.path.join(ROOT, "paper_2501_13240_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per operator launch from the committed rocprofv3 counter summary,
+    or None when the operator's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "ax_N7_convection_box_traffic.txt")
-    src = os.path.join(ROOT, "paper_2501_13240_amd", "csrc", "kernels_ax.hip")
     try:
         kv = {}
         for line in open(path):
             if ":" in line and not line.startswith(("|", "#", " ")):
                 key, val = line.split(":", 1)
                 kv[key.strip()] = val.strip()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if kv.get("kernels_ax.hip sha256") != sha:
+        if kv.get("operator sources sha256") != operator_sources_sha256():
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
