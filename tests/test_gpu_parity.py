@@ -35,19 +35,6 @@ def dev(a, dtype=torch.float64):
     return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
-@pytest.fixture(params=["plain", "nontemporal"])
-def store_form(request, monkeypatch):
-    """Which form of the in-solve operator a mesh set up in the test uses:
-    shared-copy results written with plain stores (the default up to a
-    128 MB local array) or with nontemporal ones (the default above;
-    SEM_AX_NT_BYTES=0, read at mesh set-up, forces them at any size)."""
-    if request.param == "nontemporal":
-        monkeypatch.setenv("SEM_AX_NT_BYTES", "0")
-    else:
-        monkeypatch.delenv("SEM_AX_NT_BYTES", raising=False)
-    return request.param
-
-
 def small_mesh(N, shape=(3, 2, 3), dirichlet="all", deform=True, periodic=(False, False, False)):
     return box_mesh(N, shape, (1.0, 1.5, 1.0), periodic=periodic, dirichlet=dirichlet,
                     jitter=0.05, deform=dict(a=0.15, seed=3, kind="walls") if deform else None)

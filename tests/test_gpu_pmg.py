@@ -243,7 +243,9 @@ def test_schwarz_vcycle_matches_oracle_dirichlet_cube():
     _vcycle_case(m, 7, smoother="schwarz")
 
 
-def test_schwarz_vcycle_matches_oracle_neumann_clustered_box():
+def test_schwarz_vcycle_matches_oracle_neumann_clustered_box(store_form):
+    # the order-9 level forms its smoother residuals with the split operator,
+    # in both store forms
     m, _ = config_mesh(5, shape=(4, 4, 4))
     _vcycle_case(m, 9, seed=2, smoother="schwarz")
 
@@ -277,7 +279,7 @@ def test_schwarz_bound_brackets_the_largest_eigenvalue():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_schwarz_pmg_fcg_matches_oracle(prec):
+def test_schwarz_pmg_fcg_matches_oracle(prec, store_form):
     m, fld = config_mesh(3, N=9)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, 9)
     M.setup_pmg(smoother="schwarz", **_CYCLE["schwarz"])
