@@ -248,7 +248,8 @@ sem_status sem_lmax_estimate(const sem_mesh* mesh, const double* k, double h2, i
  * x0 on entry (NULL-free: pass zeros for x0 = 0) and the copy-consistent
  * solution on return (0 at Dirichlet nodes).  With no Dirichlet node and
  * h2 = 0 the constant mode is removed from b and from x (zero mean over the
- * unique nodes).  k: DEVICE double [E][P] or NULL.  Blocks the host (it reads
+ * unique nodes), and every residual update subtracts the mean of A p, so
+ * the residual stays free of it.  k: DEVICE double [E][P] or NULL.  Blocks the host (it reads
  * residual norms).  stats may be NULL.  Returns SEM_ENOCONV / SEM_EBREAKDOWN
  * with x = last iterate and stats filled.  A mesh with no free node (every
  * node Dirichlet) returns SEM_OK at once with x = 0 and 0 iterations. */
