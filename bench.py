@@ -569,10 +569,12 @@ def small_solves(sem):
     for N in (7, 9):
         m, fld = config_mesh(1, N=N)
         M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
-        f = torch.tensor(fld["f"] * 3 * np.pi ** 2, device="cuda")
+        u_exact = fld["f"]  # the manufactured solution at the local points
+        f = torch.tensor(u_exact * 3 * np.pi ** 2, device="cuda")
         b = sem.gs(M, sem.mass(M, f))
         sem.lmax_estimate(M)
-        res = {"n_unique": M.info["n_unique"]}
+        res = {"n_unique": M.info["n_unique"],
+               "ax_fp64": ax_rate(sem, M, torch.float64, 20)}
         for name, v in variants.items():
             pmg_setup(sem, M, b, name)
             sem.solve(M, b, rtol=1e-10, **v)  # warm (graph capture, work space)
@@ -583,7 +585,10 @@ def small_solves(sem):
                     best = (x, st)
             x, st = best
             res[name] = {"ms": st["time_ms"], "iters": st["iters"], "outer": st["outer_iters"],
-                         "true_rel_res": true_rel_residual(sem, M, b, x)}
+                         "true_rel_res": true_rel_residual(sem, M, b, x),
+                         "gdof_it_s": M.info["n_unique"] * st["iters"] / (st["time_ms"] * 1e-3)
+                         / 1e9,
+                         "max_err_vs_u_exact": float(np.max(np.abs(x.cpu().numpy() - u_exact)))}
             CHECKS.add(f"cube1_N{N}", dict(cfg=1, N=N), None, name, x.cpu().numpy(), res[name])
         out[f"N{N}"] = res
         M.close()
