@@ -231,23 +231,26 @@ def true_rel_residual(sem, M, b, x, k=None, h2=0.0):
     return float(torch.sqrt(torch.sum(r * r / mult) / torch.sum(bb * bb / mult)))
 
 
-def ax_rate(sem, M, dtype, reps):
+def ax_rate(sem, M, dtype, reps, k=None, h2=0.0):
     """Stand-alone sem_ax on a mesh: median of individually event-timed applies
-    after 5 warm-ups; algorithmic bytes 64 (FP64) or 32 (FP32) per local point."""
+    after 5 warm-ups; algorithmic bytes per local point 64 (FP64) or 32 (FP32)
+    for u, G and w, plus one value each for k and, with h2 != 0, for B."""
     import torch
     u = torch.randn(M.E, M.P, dtype=dtype, device="cuda")
     w = torch.empty_like(u)
     for _ in range(5):
-        sem.ax(M, u, out=w)
+        sem.ax(M, u, k=k, h2=h2, out=w)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(reps)]
     for e0, e1 in evs:
         e0.record()
-        sem.ax(M, u, out=w)
+        sem.ax(M, u, k=k, h2=h2, out=w)
         e1.record()
     torch.cuda.synchronize()
     ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
-    nbytes = (64.0 if dtype == torch.float64 else 32.0) * M.info["n_local"]
+    vb = 8.0 if dtype == torch.float64 else 4.0
+    nbytes = (8 * vb + (vb if k is not None else 0.0) + (vb if h2 != 0.0 else 0.0)) \
+        * M.info["n_local"]
     return {"us": ms * 1e3, "gdof_s": M.info["n_unique"] / (ms * 1e-3) / 1e9,
             "algorithmic_bytes": nbytes, "gb_s": nbytes / (ms * 1e-3) / 1e9,
             "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
@@ -627,6 +630,10 @@ def gradient_timing(sem):
     for rep in range(2):
         x, k, fwd, bwd = timed_pass({})
         out = {"forward_ms": fwd, "backward_ms": bwd, "n_unique": M.info["n_unique"]}
+    # the operator with k and the h2 mass term (80 B per local point); its
+    # 168 MB stream fits in the memory-side cache, so this is no HBM figure
+    out["ax_fp64_k_h2"] = ax_rate(sem, M, torch.float64, 20, k=k0, h2=fld["h2"])
+    out["ax_fp64_k_h2"]["cache_resident"] = True
     # the same forward and backward with FP64 flexible CG preconditioned by the
     # FP32 p-multigrid cycle (k interpolated to every level); the hierarchy is
     # built and the level bounds formed outside the timing
