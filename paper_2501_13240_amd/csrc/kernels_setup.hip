@@ -19,7 +19,8 @@ __global__ __launch_bounds__(kGeoThreads) void geometry_kernel(
   __shared__ double X[3][kMaxP];
   __shared__ double D[(kMaxOrder + 1) * (kMaxOrder + 1)];
   __shared__ double w1[kMaxOrder + 1];
-  const int64_t e = blockIdx.x;
+  const int64_t e = blockIdx.x;  // one workgroup per element: the grid is E
+  (void)E;
   const int P2 = n1 * n1, P = P2 * n1;
   for (int a = threadIdx.x; a < n1 * n1; a += blockDim.x) D[a] = Dg[a];
   for (int a = threadIdx.x; a < n1; a += blockDim.x) w1[a] = rho[a];
