@@ -210,6 +210,7 @@ __device__ __forceinline__ bool cg_alpha(const double* __restrict__ part_in, int
 
 // alpha from the p.w partials; x += alpha p (not kUpdJacZ);
 // r -= alpha (w - mean_w); partials of r.r (and r.S r)
+constexpr int kPrefetch = 8;
 template <typename T, int MODE>
 __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict__ x,
                                                       const T* __restrict__ p, T* __restrict__ r,
@@ -219,6 +220,24 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
                                                       double* __restrict__ part,
                                                       CgScalars* __restrict__ sc,
                                                       double* __restrict__ ahist) {
+  // kUpdJacZ: this thread's first kPrefetch points of its chunk are requested
+  // before alpha is formed (which waits for the scalars and partial sums), so
+  // the stream starts while the block reduces
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t chunk = (nf + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = lb * chunk + threadIdx.x, hi = lb * chunk + chunk < nf ? lb * chunk + chunk : nf;
+  T pd[kPrefetch], pr[kPrefetch], pw[kPrefetch];
+  if constexpr (MODE == kUpdJacZ) {
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      const int64_t g = lo + (int64_t)j * blockDim.x;
+      if (g < hi) {
+        pd[j] = __builtin_nontemporal_load(dinv + g);
+        pr[j] = r[g];
+        pw[j] = w[g];
+      }
+    }
+  }
   if (sc->done) return;
   double alpha, mw;
   if (!cg_alpha(part_in, nblk, sc, ahist, MODE == kUpdJacZ, alpha, mw)) return;
@@ -227,14 +246,20 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
   if constexpr (MODE == kUpdJacZ) {
     // S and x (in the p update) are touched once per iteration: nontemporal,
     // so the memory-side cache keeps p, z and w, which are re-read a kernel later
-    BLOCK_CHUNK(g, nf) {
-      const T d = __builtin_nontemporal_load(dinv + g);
-      const T rg = r[g] / d - a * (w[g] - mwt);
+    auto point = [&](int64_t g, T d, T rz, T wg) {
+      const T rg = rz / d - a * (wg - mwt);
       const T zg = d * rg;
       r[g] = zg;
       v[0] += (double)rg * (double)rg;
       v[1] += (double)rg * (double)zg;
+    };
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      const int64_t g = lo + (int64_t)j * blockDim.x;
+      if (g < hi) point(g, pd[j], pr[j], pw[j]);
     }
+    for (int64_t g = lo + (int64_t)kPrefetch * blockDim.x; g < hi; g += blockDim.x)
+      point(g, __builtin_nontemporal_load(dinv + g), r[g], w[g]);
   } else {
     BLOCK_CHUNK(g, nf) {
       x[g] = x[g] + a * p[g];
@@ -290,6 +315,29 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __rest
                                                            int nblk, CgScalars* __restrict__ sc,
                                                            double* __restrict__ hist,
                                                            double* __restrict__ bhist) {
+  // ZS with 16-byte aligned vectors: this thread's first kPrefetch pairs of
+  // p, x and z are requested before the partial sums are reduced
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  const bool vec2 = ZS && aligned16(p, x, r);
+  const int64_t nh = nf / 2;
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t chunk = (nh + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = lb * chunk + threadIdx.x, hi = lb * chunk + chunk < nh ? lb * chunk + chunk : nh;
+  V2 pp[kPrefetch], px[kPrefetch], pz[kPrefetch];
+  if (vec2) {
+    const V2* p2 = reinterpret_cast<const V2*>(p);
+    const V2* x2 = reinterpret_cast<const V2*>(x);
+    const V2* z2 = reinterpret_cast<const V2*>(r);
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      const int64_t h = lo + (int64_t)j * blockDim.x;
+      if (h < hi) {
+        pp[j] = p2[h];
+        px[j] = __builtin_nontemporal_load(x2 + h);
+        pz[j] = z2[h];
+      }
+    }
+  }
   if (ZS ? !sc->pending : sc->done) return;
   const int kit = sc->kcur;
   const double rho = sc->rho2[kit & 1];
@@ -311,12 +359,19 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __rest
   }
   const T b = (T)beta;
   if constexpr (ZS) {
-    if (aligned16(p, x, r)) {
-      typedef T V2 __attribute__((ext_vector_type(2)));
+    if (vec2) {
       V2* p2 = reinterpret_cast<V2*>(p);
       V2* x2 = reinterpret_cast<V2*>(x);
       const V2* z2 = reinterpret_cast<const V2*>(r);
-      BLOCK_CHUNK(h, nf / 2) {
+#pragma unroll
+      for (int j = 0; j < kPrefetch; ++j) {
+        const int64_t h = lo + (int64_t)j * blockDim.x;
+        if (h < hi) {
+          __builtin_nontemporal_store(px[j] + a * pp[j], x2 + h);
+          p2[h] = pz[j] + b * pp[j];
+        }
+      }
+      for (int64_t h = lo + (int64_t)kPrefetch * blockDim.x; h < hi; h += blockDim.x) {
         const V2 pg = p2[h];
         __builtin_nontemporal_store(__builtin_nontemporal_load(x2 + h) + a * pg, x2 + h);
         p2[h] = z2[h] + b * pg;
