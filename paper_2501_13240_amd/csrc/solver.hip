@@ -126,6 +126,19 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_pw(int64_t nf, const int32_t
   block_partials<2>(v, part);
 }
 
+// this block's chunk of the ne partial pairs, in order (sum(w), the second
+// of a pair, serves the null-space projection only)
+__device__ __forceinline__ void epart_chunk(int64_t ne, const double* __restrict__ epart,
+                                            bool mean, double (&v)[2]) {
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t ch = (ne + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = lb * ch, hi = lo + ch < ne ? lo + ch : ne;
+  for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+    v[0] += epart[2 * e];
+    if (mean) v[1] += epart[2 * e + 1];
+  }
+}
+
 // The same for the split operator, which has already written w at the
 // single-copy free nodes [0, n1) and the partial sums (ne pairs, one per
 // wavefront of each element: p.w and sum(w) over all its copies, p.w alone
@@ -139,22 +152,25 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
     double* __restrict__ part, CgScalars* __restrict__ sc) {
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->pending = 0;
   if (sc->done) return;
-  // sum(w) serves the null-space projection only
-  const bool mean = sc->neumann != 0;
   double v[2] = {0.0, 0.0};
-  {
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t ch = (ne + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = lb * ch, hi = lo + ch < ne ? lo + ch : ne;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-      v[0] += epart[2 * e];
-      if (mean) v[1] += epart[2 * e + 1];
-    }
-  }
+  epart_chunk(ne, epart, sc->neumann != 0, v);
   BLOCK_CHUNK(i, nf - n1) {
     const int64_t g = n1 + i;
     w[g] = segment_sum<T>(perm, wL, seg[g], seg[g + 1]);
   }
+  block_partials<2>(v, part);
+}
+
+// The partial pairs alone (the split Jacobi iteration, whose residual update
+// sums the shared nodes' copies itself)
+__global__ __launch_bounds__(kVecBlock) void k_epart_sum(int64_t ne,
+                                                         const double* __restrict__ epart,
+                                                         double* __restrict__ part,
+                                                         CgScalars* __restrict__ sc) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->pending = 0;
+  if (sc->done) return;
+  double v[2] = {0.0, 0.0};
+  epart_chunk(ne, epart, sc->neumann != 0, v);
   block_partials<2>(v, part);
 }
 
@@ -270,6 +286,69 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
       if (MODE == kUpdJacR) v[1] += rd * rd * (double)dinv[g];
     }
   }
+  block_partials<2>(v, part);
+}
+
+// kUpdJacZ for the split operator with the segmented sum folded in: w is
+// read from the operator's output at the single-copy nodes [0, n1) and summed
+// over the copies at their surface slots (seg, perm into wL) at the shared
+// nodes [n1, nf), which the iteration then never stores.  Each block takes
+// one chunk of either range, so the gathers spread over the whole grid.
+template <typename T>
+__global__ __launch_bounds__(kVecBlock) void k_update_split(
+    int64_t n1, int64_t nf, const int32_t* __restrict__ seg, const int32_t* __restrict__ perm,
+    const T* __restrict__ wL, T* __restrict__ r, const T* __restrict__ w,
+    const T* __restrict__ dinv, const double* __restrict__ part_in, int nblk,
+    double* __restrict__ part, CgScalars* __restrict__ sc, double* __restrict__ ahist) {
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t c1 = (n1 + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = lb * c1 + threadIdx.x, hi = lb * c1 + c1 < n1 ? lb * c1 + c1 : n1;
+  T pd[kPrefetch], pr[kPrefetch], pw[kPrefetch];
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j) {
+    const int64_t g = lo + (int64_t)j * blockDim.x;
+    if (g < hi) {
+      pd[j] = __builtin_nontemporal_load(dinv + g);
+      pr[j] = r[g];
+      pw[j] = w[g];
+    }
+  }
+  if (sc->done) return;
+  double alpha, mw;
+  if (!cg_alpha(part_in, nblk, sc, ahist, true, alpha, mw)) return;
+  const T a = (T)alpha, mwt = (T)mw;
+  double v[2] = {0.0, 0.0};
+  auto point = [&](int64_t g, T d, T rz, T wg) {
+    const T rg = rz / d - a * (wg - mwt);
+    const T zg = d * rg;
+    r[g] = zg;
+    v[0] += (double)rg * (double)rg;
+    v[1] += (double)rg * (double)zg;
+  };
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j) {
+    const int64_t g = lo + (int64_t)j * blockDim.x;
+    if (g < hi) point(g, pd[j], pr[j], pw[j]);
+  }
+  // the shared nodes' chains (offsets -> copy indices -> copy values) are
+  // interleaved with the single-copy stream: each step takes one point of
+  // each range, so the stream's loads are in flight while a chain waits
+  const int64_t ns = nf - n1;
+  const int64_t c2 = (ns + gridDim.x - 1) / gridDim.x;
+  const int64_t lo2 = lb * c2 + threadIdx.x, hi2 = lb * c2 + c2 < ns ? lb * c2 + c2 : ns;
+  int64_t g = lo + (int64_t)kPrefetch * blockDim.x;
+  for (int64_t i = lo2; i < hi2; i += blockDim.x) {
+    const int64_t gs = n1 + i;
+    const bool one = g < hi;
+    const int64_t gq = one ? g : gs;
+    const T d1 = __builtin_nontemporal_load(dinv + gq), r1 = r[gq], w1 = w[gq];
+    const T ds = __builtin_nontemporal_load(dinv + gs), rs = r[gs];
+    const T ws = segment_sum<T>(perm, wL, seg[gs], seg[gs + 1]);
+    if (one) point(g, d1, r1, w1);
+    point(gs, ds, rs, ws);
+    g += blockDim.x;
+  }
+  for (; g < hi; g += blockDim.x) point(g, __builtin_nontemporal_load(dinv + g), r[g], w[g]);
   block_partials<2>(v, part);
 }
 
@@ -1143,6 +1222,18 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   };
   auto iteration = [&](hipStream_t ss) -> sem_status {
     sem_status e;
+    if (split && jac) {
+      // the segmented sum folded into the residual update
+      if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile, w, epart, a.neumann))) return e;
+      hipLaunchKernelGGL(k_epart_sum, dim3(nb), dim3(kVecBlock), 0, ss, nparts, epart, partA, sc);
+      hipLaunchKernelGGL((k_update_split<T>), dim3(nb), dim3(kVecBlock), 0, ss, m->n_single, nf,
+                         m->fseg.as<int32_t>(), m->fperm2.as<int32_t>(), wL, r, w, a.dinv, partA,
+                         (int)nb, partB, sc, ahist);
+      hipLaunchKernelGGL((k_pupdate_jac<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, x, r,
+                         a.dinv, partB, (int)nb, sc, hist, bhist);
+      SEM_CHECK_LAUNCH("CG iteration");
+      return SEM_OK;
+    }
     if (split) {
       if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile, w, epart, a.neumann))) return e;
       hipLaunchKernelGGL((k_gsum_split_pw<T>), dim3(nb), dim3(kVecBlock), 0, ss, m->n_single,
