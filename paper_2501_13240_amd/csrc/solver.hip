@@ -162,7 +162,8 @@ __global__ __launch_bounds__(kVecBlock) void k_gsum_split_pw(
 }
 
 // The partial pairs alone (the split Jacobi iteration, whose residual update
-// sums the shared nodes' copies itself)
+// sums the shared nodes' copies itself), on a grid of kEpartBlocks
+constexpr int kEpartBlocks = 64;
 __global__ __launch_bounds__(kVecBlock) void k_epart_sum(int64_t ne,
                                                          const double* __restrict__ epart,
                                                          double* __restrict__ part,
@@ -1223,12 +1224,15 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
   auto iteration = [&](hipStream_t ss) -> sem_status {
     sem_status e;
     if (split && jac) {
-      // the segmented sum folded into the residual update
+      // the segmented sum folded into the residual update; the operator's
+      // sums reduced by a grid of kEpartBlocks (a short head reduction for
+      // every block of the update)
       if ((e = apply_op<T>(m, W, op_it, p, wL, ss, a.profile, w, epart, a.neumann))) return e;
-      hipLaunchKernelGGL(k_epart_sum, dim3(nb), dim3(kVecBlock), 0, ss, nparts, epart, partA, sc);
+      hipLaunchKernelGGL(k_epart_sum, dim3(kEpartBlocks), dim3(kVecBlock), 0, ss, nparts, epart,
+                         partA, sc);
       hipLaunchKernelGGL((k_update_split<T>), dim3(nb), dim3(kVecBlock), 0, ss, m->n_single, nf,
                          m->fseg.as<int32_t>(), m->fperm2.as<int32_t>(), wL, r, w, a.dinv, partA,
-                         (int)nb, partB, sc, ahist);
+                         kEpartBlocks, partB, sc, ahist);
       hipLaunchKernelGGL((k_pupdate_jac<T, true>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, x, r,
                          a.dinv, partB, (int)nb, sc, hist, bhist);
       SEM_CHECK_LAUNCH("CG iteration");
