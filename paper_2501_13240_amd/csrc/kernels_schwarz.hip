@@ -313,13 +313,125 @@ __global__ __launch_bounds__(64 * kFdmWaves) void fdm_wave_kernel(
   for (int q = lane; q < P3; q += 64) out[e * P3 + q] = A[q];
 }
 
+// The small-box kernel on a persistent grid: each wavefront walks the
+// elements w0, w0 + W, ... (W wavefronts in the grid) and keeps the next
+// element's subdomain map (during the first transform), residual gathers and
+// S, lam factors (during the others) in flight, as fdm_pipe_kernel does per
+// workgroup; each transform's fragments of S are loaded once for its tiles.
+template <int n, typename T>
+__global__ __launch_bounds__(64 * kFdmWaves) void fdm_wave_pipe_kernel(
+    int64_t E, const int32_t* __restrict__ xmap, const T* __restrict__ S,
+    const T* __restrict__ lam, const T* __restrict__ r, T* __restrict__ out,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int P2 = n * n, P3 = P2 * n, NT = (P2 + 15) / 16;
+  constexpr int NF = 3 * P2 + 3 * n;  // S then lam of one element
+  constexpr int PPT = (P3 + 63) / 64, FPT = (NF + 63) / 64;
+  __shared__ T sA[kFdmWaves][P3];
+  __shared__ T sB[kFdmWaves][P3];
+  __shared__ T sF[kFdmWaves][NF];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T* A = sA[w];
+  T* B = sB[w];
+  T* F = sF[w];
+  const int64_t nw = (int64_t)gridDim.x * kFdmWaves;
+  int64_t e = (int64_t)blockIdx.x * kFdmWaves + w;
+  if (e >= E) return;  // the whole wavefront (no workgroup barrier follows)
+  int32_t gi[PPT];
+  T rv[PPT], fv[FPT];
+  T af[(n + 3) / 4];
+  auto load_map = [&](int64_t el) {
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int q = lane + 64 * s;
+      gi[s] = q < P3 ? xmap[el * P3 + q] : -1;
+    }
+  };
+  auto load_vals = [&](int64_t el) {
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) rv[s] = gi[s] >= 0 ? r[gi[s]] : T(0);
+#pragma unroll
+    for (int s = 0; s < FPT; ++s) {
+      const int f = lane + 64 * s;
+      fv[s] = f < 3 * P2 ? S[el * 3 * P2 + f] : f < NF ? lam[el * 3 * n + (f - 3 * P2)] : T(0);
+    }
+  };
+  load_map(e);
+  load_vals(e);
+  for (; e < E; e += nw) {
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+      const int q = lane + 64 * s;
+      if (q < P3) A[q] = rv[s];
+    }
+#pragma unroll
+    for (int s = 0; s < FPT; ++s) {
+      const int f = lane + 64 * s;
+      if (f < NF) F[f] = fv[s];
+    }
+    wave_sync();
+    const int64_t en = e + nw;
+    const bool more = en < E;
+    if (more) load_map(en);
+    fdm_frag<n, T>(F, true, lane, af);
+    for (int tile = 0; tile < NT; ++tile) fdm_tile_f<n, T, 0>(A, B, af, tile, lane);
+    wave_sync();
+    if (more) load_vals(en);
+    fdm_frag<n, T>(F + P2, true, lane, af);
+    for (int tile = 0; tile < NT; ++tile) fdm_tile_f<n, T, 1>(B, A, af, tile, lane);
+    wave_sync();
+    fdm_frag<n, T>(F + 2 * P2, true, lane, af);
+    for (int tile = 0; tile < NT; ++tile) fdm_tile_f<n, T, 2>(A, B, af, tile, lane);
+    wave_sync();
+    const T* L = F + 3 * P2;
+    for (int q = lane; q < P3; q += 64) {
+      const int a = q % n, b = (q / n) % n, c = q / P2;
+      B[q] = B[q] / (L[a] + L[n + b] + L[2 * n + c]);
+    }
+    wave_sync();
+    fdm_frag<n, T>(F + 2 * P2, false, lane, af);
+    for (int tile = 0; tile < NT; ++tile) fdm_tile_f<n, T, 2>(B, A, af, tile, lane);
+    wave_sync();
+    fdm_frag<n, T>(F + P2, false, lane, af);
+    for (int tile = 0; tile < NT; ++tile) fdm_tile_f<n, T, 1>(A, B, af, tile, lane);
+    wave_sync();
+    fdm_frag<n, T>(F, false, lane, af);
+    for (int tile = 0; tile < NT; ++tile) fdm_tile_f<n, T, 0>(B, A, af, tile, lane);
+    wave_sync();
+    for (int q = lane; q < P3; q += 64) out[e * P3 + q] = A[q];
+    wave_sync();  // A and F are restaged for the next element
+  }
+}
+
+#ifndef SEM_FDM_WAVE_PIPE
+#define SEM_FDM_WAVE_PIPE 1
+#endif
+
 template <int n, typename T>
 hipError_t run_fdm(int64_t E, const int32_t* xmap, const T* S, const T* lam, const T* r, T* out,
                    const int32_t* skip, hipStream_t s) {
   if constexpr (n <= 8) {
+#if SEM_FDM_WAVE_PIPE
+    // persistent grid: the resident workgroups of the device, at most one
+    // wavefront per element
+    static int resident = 0;
+    if (resident == 0) {
+      int dev = 0, cus = 0, per_cu = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fdm_wave_pipe_kernel<n, T>,
+                                                       64 * kFdmWaves, 0) != hipSuccess)
+        return hipErrorUnknown;
+      resident = std::max(1, cus * per_cu);
+    }
+    const int64_t grid = std::min<int64_t>((E + kFdmWaves - 1) / kFdmWaves, resident);
+    hipLaunchKernelGGL((fdm_wave_pipe_kernel<n, T>), dim3((unsigned)grid), dim3(64 * kFdmWaves),
+                       0, s, E, xmap, S, lam, r, out, skip);
+#else
     const int64_t grid = (E + kFdmWaves - 1) / kFdmWaves;
     hipLaunchKernelGGL((fdm_wave_kernel<n, T>), dim3((unsigned)grid), dim3(64 * kFdmWaves), 0, s,
                        E, xmap, S, lam, r, out, skip);
+#endif
   } else {
     constexpr int NW = fdm_waves(n);
 #if SEM_FDM_PIPE
