@@ -6,12 +6,15 @@
 // Vectors of the solve live on the free unique nodes (length n_free; the
 // n_single nodes with one local copy first).  One iteration is
 //   ax (gathers p through lmap, writes the element-local result w_L; from
-//   N = 5 on it writes w at the single-copy nodes directly, with their p.w)
+//   N = 5 on it writes w at the single-copy nodes directly, and each
+//   wavefront's p.w over all its copies)
 //   -> segmented sum w = R Q^T w_L fused with p.w (over the shared nodes)
 //   -> alpha on the device -> residual update fused with r.r (and r.S r)
 //   -> beta on the device -> p update.  Jacobi keeps z = S r in place of r
 //   and applies x += alpha p in the p update; the other preconditioners
-//   update x with r.
+//   update x with r.  Jacobi from N = 5 on folds the segmented sum into the
+//   residual update (w is summed there at the shared nodes, never stored),
+//   after a short kernel that reduces the operator's p.w sums.
 // All scalars stay on the device (CgScalars); the host only polls the `done`
 // flag every few iterations with one chunk of iterations always queued ahead,
 // and every kernel of a finished solve returns at once.  Reductions use a
