@@ -361,10 +361,10 @@ def pmg_cube_iteration_bytes(nel=32, orders=(9, 4, 2, 1), smooth_order=4, coarse
     add("ax FP64 in-solve (64 B per local point)", 64.0 * nL)
     add("shared-node sum (12 B per shared copy, 12 B per shared node)",
         12.0 * (nL - n1) + 12.0 * (nf - n1))
-    add("CG update (48 B per free node)", 48.0 * nf)
+    add("CG update (24 B per free node)", 24.0 * nf)
     add("residual to FP32 (12 B per free node)", 12.0 * nf)
     add("z and dots (28 B per free node)", 28.0 * nf)
-    add("p update (24 B per free node)", 24.0 * nf)
+    add("x and p update (40 B per free node)", 40.0 * nf)
     # V-cycle (FP32)
     for lev, N in enumerate(orders):
         nL, nf, n1, bp, bc = sizes(N)

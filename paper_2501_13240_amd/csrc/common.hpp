@@ -102,8 +102,9 @@ struct CgScalars {
   int32_t flexible; // 1 = Polak-Ribiere beta
   int32_t kcur;     // index of the iteration in progress (set by the update kernel)
   double rho2[2];   // r.z of iteration k in slot k & 1
-  int32_t pending;  // Jacobi: 1 = x += alpha p of iteration kcur still to apply
-                    // (set by the update kernel, cleared by the next segmented sum)
+  int32_t pending;  // 1 = x += alpha p of iteration kcur still to apply (set by the
+                    // residual update, cleared by the next segmented sum; applied by
+                    // the direction update)
   int32_t pad2;
 };
 

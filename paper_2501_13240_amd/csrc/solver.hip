@@ -10,11 +10,11 @@
 //   wavefront's p.w over all its copies)
 //   -> segmented sum w = R Q^T w_L fused with p.w (over the shared nodes)
 //   -> alpha on the device -> residual update fused with r.r (and r.S r)
-//   -> beta on the device -> p update.  Jacobi keeps z = S r in place of r
-//   and applies x += alpha p in the p update; the other preconditioners
-//   update x with r.  Jacobi from N = 5 on folds the segmented sum into the
-//   residual update (w is summed there at the shared nodes, never stored),
-//   after a short kernel that reduces the operator's p.w sums.
+//   -> beta on the device -> p update, which also applies x += alpha p (it
+//   reads p anyway).  Jacobi keeps z = S r in place of r, and from N = 5 on
+//   folds the segmented sum into the residual update (w is summed there at
+//   the shared nodes, never stored), after a short kernel that reduces the
+//   operator's p.w sums.
 // All scalars stay on the device (CgScalars); the host only polls the `done`
 // flag every few iterations with one chunk of iterations always queued ahead,
 // and every kernel of a finished solve returns at once.  Reductions use a
@@ -181,8 +181,9 @@ __global__ __launch_bounds__(kVecBlock) void k_epart_sum(int64_t ne,
 // What the residual vector of a CG iteration holds, and which partials the
 // update forms: r (and r.r only), r (r.r and r.S r, Jacobi), or z = S r in
 // place of r (Jacobi: r = z / S is recovered in registers, so the direction
-// update p = z + beta p reads neither r nor S).  In the last mode x += alpha p
-// is left to the direction update, which reads p anyway.
+// update p = z + beta p reads neither r nor S).  In the first and the last
+// mode x += alpha p is left to the direction update (k_pupdate_flex,
+// k_pupdate_jac), which reads p anyway.
 enum UpdMode { kUpdR = 0, kUpdJacR = 1, kUpdJacZ = 2 };
 
 // The Jacobi p update walks pairs of consecutive elements (one 16-byte access
@@ -228,7 +229,7 @@ __device__ __forceinline__ bool cg_alpha(const double* __restrict__ part_in, int
   return true;
 }
 
-// alpha from the p.w partials; x += alpha p (not kUpdJacZ);
+// alpha from the p.w partials; x += alpha p (kUpdJacR only);
 // r -= alpha (w - mean_w); partials of r.r (and r.S r)
 constexpr int kPrefetch = 8;
 template <typename T, int MODE>
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
   }
   if (sc->done) return;
   double alpha, mw;
-  if (!cg_alpha(part_in, nblk, sc, ahist, MODE == kUpdJacZ, alpha, mw)) return;
+  if (!cg_alpha(part_in, nblk, sc, ahist, MODE != kUpdJacR, alpha, mw)) return;
   const T a = (T)alpha, mwt = (T)mw;
   double v[2] = {0.0, 0.0};
   if constexpr (MODE == kUpdJacZ) {
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(kVecBlock) void k_update(int64_t nf, T* __restrict_
       point(g, __builtin_nontemporal_load(dinv + g), r[g], w[g]);
   } else {
     BLOCK_CHUNK(g, nf) {
-      x[g] = x[g] + a * p[g];
+      if constexpr (MODE == kUpdJacR) x[g] = x[g] + a * p[g];
       const T rg = r[g] - a * (w[g] - mwt);
       r[g] = rg;
       const double rd = (double)rg;
@@ -477,14 +478,24 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_jac(int64_t nf, T* __rest
 }
 
 // flexible CG: beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha z.(w - mean_w) / rho_k
-// from the preconditioner pass's partials (z.r, z.(w - mean_w)); p = z + beta p
+// from the preconditioner pass's partials (z.r, z.(w - mean_w)); p = z + beta p.
+// x += alpha p (alpha of the residual update) is applied here first, also in
+// the iteration that stops the solve (at the preconditioner's convergence
+// gate, or here on a breakdown); the guard is the pending flag, which the
+// residual update sets and the next iteration's segmented sum clears.
 template <typename T, typename Tz>
 __global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, T* __restrict__ p,
+                                                            T* __restrict__ x,
                                                             const Tz* __restrict__ z,
                                                             const double* __restrict__ part_in,
                                                             int nblk, CgScalars* __restrict__ sc,
                                                             double* __restrict__ bhist) {
-  if (sc->done) return;
+  if (!sc->pending) return;
+  const T a = (T)sc->alpha;
+  if (sc->done) {
+    BLOCK_CHUNK(g, nf) x[g] = x[g] + a * p[g];
+    return;
+  }
   const int kit = sc->kcur;
   double S[2];
   block_total<2>(part_in, nblk, S);
@@ -495,6 +506,7 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, T* __res
       sc->status = 3;
       sc->done = 1;
     }
+    BLOCK_CHUNK(g, nf) x[g] = x[g] + a * p[g];
     return;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -503,7 +515,11 @@ __global__ __launch_bounds__(kVecBlock) void k_pupdate_flex(int64_t nf, T* __res
     if (bhist) bhist[kit] = beta;
   }
   const T b = (T)beta;
-  BLOCK_CHUNK(g, nf) p[g] = (T)z[g] + b * p[g];
+  BLOCK_CHUNK(g, nf) {
+    const T pg = p[g];
+    x[g] = x[g] + a * pg;
+    p[g] = (T)z[g] + b * pg;
+  }
 }
 
 // ----------------------------------------------------- init / misc kernels
@@ -687,21 +703,20 @@ __global__ __launch_bounds__(kVecBlock) void k_cheb_step(
 // z.(w - mean_w) partials for beta.  z is formed in Tp arithmetic anyway,
 // so storing it in Tp loses nothing.
 
-// alpha; x += alpha p; r -= alpha (w - mean_w); partials of r.r; d0 = c0 S r
+// alpha; r -= alpha (w - mean_w); partials of r.r; d0 = c0 S r (x += alpha p
+// is left to k_pupdate_flex)
 template <typename T, typename Tp>
 __global__ __launch_bounds__(kVecBlock) void k_update_cheb0(
-    int64_t nf, T* __restrict__ x, const T* __restrict__ p, T* __restrict__ r,
-    const T* __restrict__ w, const Tp* __restrict__ sinv, Tp* __restrict__ d0, double c0,
-    const double* __restrict__ part_in, int nblk, double* __restrict__ part,
-    CgScalars* __restrict__ sc, double* __restrict__ ahist) {
+    int64_t nf, T* __restrict__ r, const T* __restrict__ w, const Tp* __restrict__ sinv,
+    Tp* __restrict__ d0, double c0, const double* __restrict__ part_in, int nblk,
+    double* __restrict__ part, CgScalars* __restrict__ sc, double* __restrict__ ahist) {
   if (sc->done) return;
   double alpha, mw;
-  if (!cg_alpha(part_in, nblk, sc, ahist, false, alpha, mw)) return;
+  if (!cg_alpha(part_in, nblk, sc, ahist, true, alpha, mw)) return;
   const T a = (T)alpha, mwt = (T)mw;
   const Tp c = (Tp)c0;
   double v[2] = {0.0, 0.0};
   BLOCK_CHUNK(g, nf) {
-    x[g] = x[g] + a * p[g];
     const T rg = r[g] - a * (w[g] - mwt);
     r[g] = rg;
     d0[g] = c * sinv[g] * (Tp)rg;
@@ -1203,7 +1218,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
     cheb_coeffs(fu.order, fu.lmax, fu.kind, &fc0, fca, fcb);
   }
   auto fused_pass = [&](hipStream_t ss) -> sem_status {
-    hipLaunchKernelGGL((k_update_cheb0<T, Tp>), dim3(nb), dim3(kVecBlock), 0, ss, nf, x, p, r, w,
+    hipLaunchKernelGGL((k_update_cheb0<T, Tp>), dim3(nb), dim3(kVecBlock), 0, ss, nf, r, w,
                        fu.dinv, fd, fc0, partA, (int)nb, partB, sc, ahist);
     for (int k = 1; k < fu.order; ++k) {
       const hipError_t he = launch_ax_split<Tp>(m, fd, fwf, fwL, nullptr, false, fop.k, fop.h2,
@@ -1220,7 +1235,7 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
       else SEM_FSTEP(false, false);
 #undef SEM_FSTEP
     }
-    hipLaunchKernelGGL((k_pupdate_flex<T, Tp>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, fz,
+    hipLaunchKernelGGL((k_pupdate_flex<T, Tp>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, x, fz,
                        partC, (int)nb, sc, bhist);
     return SEM_OK;
   };
@@ -1269,8 +1284,8 @@ sem_status cg_solve(const sem_mesh* m, SolveWork& W, const CgArgs<T, Tp>& a, CgR
       cg.part_out = partC;
       cg.hist = hist;
       if ((e = a.cheb(m, W, r, z, cg, ss, nullptr))) return e;
-      hipLaunchKernelGGL((k_pupdate_flex<T, T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, z, partC,
-                         (int)nb, sc, bhist);
+      hipLaunchKernelGGL((k_pupdate_flex<T, T>), dim3(nb), dim3(kVecBlock), 0, ss, nf, p, x, z,
+                         partC, (int)nb, sc, bhist);
     }
     SEM_CHECK_LAUNCH("CG iteration");
     return SEM_OK;

@@ -419,15 +419,20 @@ def test_neumann_cube_full_size_solves_true_residual_by_oracle():
           f"{rel(sol['fp64_cg_fp32_pmg'], sol['fp64_jacobi_cg']):.2e}", flush=True)
 
 
+@pytest.mark.parametrize("N", [4, 5])  # gather-form / split operator
 @pytest.mark.parametrize("profile", [False, True])  # graph replay / eager launches
-def test_stopped_solve_equals_fixed_solve_of_same_length(profile):
+def test_stopped_solve_equals_fixed_solve_of_same_length(profile, N):
     """A solve that stops on the tolerance applies its last x update exactly
     once: the launches queued after the stop leave x alone, and x equals that
-    of a fixed-length solve of the same iteration count, bit for bit."""
-    m, fld = config_mesh(1, N=5)
+    of a fixed-length solve of the same iteration count, bit for bit.  The x
+    update runs in the direction update for every preconditioner (Jacobi;
+    Chebyshev inside the CG at N = 5, as a separate pass at N = 4; the
+    p-multigrid V-cycle)."""
+    m, fld = config_mesh(1, N=N)
     M = sem.Mesh(m.xyz, m.gid, m.dirichlet, m.N)
+    M.setup_pmg()
     b = sem.gs(M, sem.mass(M, dev(fld["f"])))
-    for precond in ("jacobi", "chebyshev"):
+    for precond in ("jacobi", "chebyshev", "pmg"):
         x, st = sem.solve(M, b, precond=precond, rtol=1e-9, profile=profile)
         n = st["iters"]
         assert st["converged"] == 1
