@@ -664,7 +664,9 @@ def gradient_timing(sem):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs the single-GPU path only; the "
+                                   "multi-GPU decomposition is a design, not code: --gpus "
+                                   "must be 1"}))
         sys.exit(2)
 
     import torch

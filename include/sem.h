@@ -56,7 +56,7 @@ typedef enum {
   SEM_EDEVICE = -3,    /* HIP runtime error */
   SEM_ENOCONV = -4,    /* solve hit its iteration limit; x holds the last iterate */
   SEM_EBREAKDOWN = -5, /* CG breakdown (p.Ap <= 0 or not finite); x holds the last iterate */
-  SEM_ENOTSUP = -6     /* valid request that this build does not implement */
+  SEM_ENOTSUP = -6     /* valid request that the library does not implement */
 } sem_status;
 
 /* Arithmetic of an operator apply or of a preconditioner.
